@@ -1,0 +1,168 @@
+"""Oracle for brute-force incoherent de-dispersion -- TEST INFRASTRUCTURE ONLY.
+
+A plain, slow, obviously correct CPU reference written from the paper
+("A GPU-based survey for millisecond radio transients using ARTEMIS").  Only the
+test suite, the smoke check and the CPU-baseline leg of the benchmark may import
+it.  It shares no code with the GPU library (``paper_1111_6399_amd``) and
+neither imports the other; inputs come from the seeded generators in
+``paper_1111_6399_amd.workloads``, which hold none of the method's arithmetic.
+
+Functions and the passages they follow:
+
+* :func:`shift_table` -- per-channel dispersion delays in samples, section
+  "Searching for radio transients" (quadratic cold-plasma law, DM as the single
+  free parameter).  Constant 4148.808 s MHz^2 pc^-1 cm^3, delays relative to the
+  top of the band, round half up.  Binary64, fixed operation order, no fused
+  multiply-add (plain C, ``-ffp-contract=off``).
+* :func:`dedisperse` -- ``out[d][t] = sum_c in[c][t + shift[c][d]]``: shift each
+  channel, then integrate over frequency, for every trial DM (sections
+  "Searching for radio transients" and "Acceleration via GPU computing").
+  Binary64 accumulation for float input, int64 for uint8 input.
+* :func:`stream_reference` -- the same sum over a stream cut into blocks, with a
+  zero history before the first block (the paper does not describe block
+  buffering; this is the reading the streaming tests use).
+
+Every function here is pinned by ``tests/test_oracle_pins.py`` against results
+the mathematics fixes (exact rational arithmetic, closed forms, invariants, an
+independent dense-matrix formulation on tiny grids).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dedisp_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle into ``oracle/liboracle.so`` (gcc, OpenMP, no FMA contraction)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
+           "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    build(force=False)
+    lib = ctypes.CDLL(_LIB)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    f64p = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_shift_table.restype = ctypes.c_int64
+    lib.oracle_shift_table.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       f64p, ctypes.c_int, i32p]
+    common = [ctypes.c_int64, ctypes.c_int, i32p, ctypes.c_int, i32p, ctypes.c_int, ctypes.c_int64,
+              ctypes.c_int64]
+    lib.oracle_dedisperse_f32.restype = None
+    lib.oracle_dedisperse_f32.argtypes = [ctypes.c_void_p] + common + [ctypes.c_void_p]
+    lib.oracle_dedisperse_u8.restype = None
+    lib.oracle_dedisperse_u8.argtypes = [ctypes.c_void_p] + common + [ctypes.c_void_p]
+    lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_num_threads.argtypes = []
+    _lib = lib
+    return lib
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use on this host."""
+    return int(_load().oracle_num_threads())
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def shift_table(nchans: int, f_top: float, df: float, tsamp: float, dm_list) -> tuple[np.ndarray, int]:
+    """Integer delay of every (channel, trial DM) in samples.
+
+    Returns ``(shift, max_shift)`` with ``shift`` an int32 array of shape
+    ``(nchans, ndm)``: ``shift[c][d] = round_half_up(DM_d * k_c)`` with
+    ``f_c = f_top - c*df`` and ``k_c = 4148.808*(1/f_c^2 - 1/f_top^2)/tsamp``
+    (frequencies in MHz, tsamp in seconds).  Section "Searching for radio
+    transients": the delay follows the quadratic cold-plasma law and depends on
+    DM alone.
+    """
+    dm = np.ascontiguousarray(np.asarray(dm_list, dtype=np.float64))
+    ndm = int(dm.shape[0])
+    if nchans <= 0 or ndm <= 0:
+        raise ValueError("nchans and ndm must be positive")
+    if not (df > 0 and tsamp > 0 and f_top > 0 and f_top - (nchans - 1) * df > 0):
+        raise ValueError("band must be positive and descending")
+    if not np.all(np.isfinite(dm)) or np.any(dm < 0):
+        raise ValueError("trial DMs must be finite and non-negative")
+    out = np.empty((nchans, ndm), dtype=np.int32)
+    m = _load().oracle_shift_table(int(nchans), float(f_top), float(df), float(tsamp),
+                                   _ptr(dm, ctypes.c_double), ndm, _ptr(out, ctypes.c_int32))
+    if m < 0:
+        raise ValueError("a delay does not fit in int32")
+    return out, int(m)
+
+
+def dedisperse(data: np.ndarray, shift: np.ndarray, nsamp: int, rows=None,
+               t_begin: int = 0, t_count: int | None = None) -> np.ndarray:
+    """``out[i][t] = sum_c data[c][t_begin + t + shift[c][rows[i]]]``.
+
+    ``data`` is ``(nchans, >= nsamp + max(shift))`` float32, float16 or uint8.
+    float16 input is widened exactly to float32 first.  Returns float64 for
+    float input and int64 for uint8 input, shape ``(len(rows), t_count)``.
+    """
+    nchans, ndm = shift.shape
+    if data.ndim != 2 or data.shape[0] != nchans:
+        raise ValueError("data must be (nchans, samples)")
+    rows = np.arange(ndm, dtype=np.int32) if rows is None else np.ascontiguousarray(rows, dtype=np.int32)
+    if t_count is None:
+        t_count = nsamp - t_begin
+    if t_begin < 0 or t_count < 0 or t_begin + t_count > nsamp:
+        raise ValueError("time range outside [0, nsamp)")
+    if rows.size and (rows.min() < 0 or rows.max() >= ndm):
+        raise ValueError("row index out of range")
+    if nsamp + int(shift.max(initial=0)) > data.shape[1]:
+        raise ValueError("data rows shorter than nsamp + max_shift")
+    sh = np.ascontiguousarray(shift, dtype=np.int32)
+    if data.dtype == np.float16:
+        data = data.astype(np.float32)
+    lib = _load()
+    if data.dtype == np.float32:
+        out = np.empty((rows.size, t_count), dtype=np.float64)
+        fn = lib.oracle_dedisperse_f32
+    elif data.dtype == np.uint8:
+        out = np.empty((rows.size, t_count), dtype=np.int64)
+        fn = lib.oracle_dedisperse_u8
+    else:
+        raise TypeError("unsupported input dtype %s" % data.dtype)
+    if data.strides[1] != data.itemsize:
+        data = np.ascontiguousarray(data)
+    stride = data.strides[0] // data.itemsize
+    fn(data.ctypes.data, int(stride), int(nchans), _ptr(sh, ctypes.c_int32), int(ndm),
+       _ptr(rows, ctypes.c_int32), int(rows.size), int(t_begin), int(t_count), out.ctypes.data)
+    return out
+
+
+def stream_reference(stream: np.ndarray, shift: np.ndarray, max_shift: int, block: int,
+                     b: int, rows=None) -> np.ndarray:
+    """Output block ``b`` of a beam streamed in blocks of ``block`` samples.
+
+    ``stream`` is ``(nchans, n)`` holding the blocks back to back.  The history
+    before sample 0 is zero.  Output block ``b`` holds the de-dispersed series
+    at stream times ``[b*block - max_shift, (b+1)*block - max_shift)``, i.e. the
+    sum over the ``max_shift`` samples of history plus the new block.
+    """
+    nchans = stream.shape[0]
+    lo = b * block - max_shift
+    hi = (b + 1) * block
+    padded = np.zeros((nchans, block + max_shift), dtype=stream.dtype)
+    src_lo = max(lo, 0)
+    padded[:, src_lo - lo:] = stream[:, src_lo:hi]
+    return dedisperse(padded, shift, block, rows=rows)
