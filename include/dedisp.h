@@ -1,0 +1,226 @@
+/*
+ * dedisp.h -- brute-force incoherent de-dispersion on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (paper: Armour et al., "A GPU-based survey for millisecond radio
+ * transients using ARTEMIS", sections "Searching for radio transients" and
+ * "Acceleration via GPU computing"): every frequency channel of a filterbank
+ * (channels x time samples of total intensity) is shifted in time by the
+ * dispersion delay of a trial dispersion measure (DM), then the channels are
+ * summed.  For every trial d and output sample t
+ *
+ *     out[d][t] = sum over c of in[c][t + shift[c][d]]
+ *
+ *     shift[c][d] = round_half_up(DM_d * k_c)
+ *     k_c         = 4148.808 * (1/(f_c*f_c) - 1/(f_top*f_top)) / tsamp
+ *     f_c         = f_top - c*df            (MHz; channel 0 is the highest)
+ *
+ * The delay table is computed on the host in IEEE binary64 in exactly this
+ * order, without fused multiply-add, so it is reproducible bit for bit.
+ *
+ * Conventions for every call below
+ *  - Return value: a dedisp_status code.  On any error the out-parameters are
+ *    left untouched.  Arguments are checked before any GPU call, so argument
+ *    errors never touch the device.
+ *  - "device pointer": memory on the current HIP device (hipMalloc or torch
+ *    CUDA/ROCm tensors).  "stream": a hipStream_t passed as void*; NULL means
+ *    the default stream.  Launches are asynchronous on that stream; a device
+ *    fault surfaces as DEDISP_ERR_DEVICE at a later synchronising call.
+ *  - Layouts are row-major and dense: input [nchans][nsamp + max_shift],
+ *    output [ndm][nsamp].  Input must be 16-byte aligned.
+ *  - Output element type: int32 for DEDISP_U8 input (exact integer sums),
+ *    float32 for DEDISP_F16 / DEDISP_F32 input.  Float sums use a fixed
+ *    order: channels in ascending order in blocks of 32, each block summed
+ *    into a float32 partial that is then added to the running float32 total.
+ *    Every kernel variant, the batched launch and the streaming server follow
+ *    this order, so their float32 results are identical to each other.
+ *  - Ownership: a plan owns its delay table (host copy and one device copy per
+ *    device it has run on).  The caller owns every buffer and stream passed in.
+ *    Plans are immutable after creation apart from the kernel-variant choice;
+ *    concurrent executes of one plan on different streams are allowed, but a
+ *    variant change must not race with them.
+ */
+#ifndef DEDISP_H
+#define DEDISP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dedisp_plan_s *dedisp_plan;
+typedef struct dedisp_batch_s *dedisp_batch;
+typedef struct dedisp_server_s *dedisp_server;
+
+/* Input sample types. */
+enum dedisp_dtype {
+    DEDISP_U8 = 0,   /* unsigned 8-bit samples, int32 output, exact */
+    DEDISP_F16 = 1,  /* IEEE half samples, float32 accumulation and output */
+    DEDISP_F32 = 2   /* IEEE single samples, float32 accumulation and output */
+};
+
+enum dedisp_status {
+    DEDISP_OK = 0,
+    DEDISP_ERR_INVALID_ARG = 1,   /* an argument is out of its documented range */
+    DEDISP_ERR_OUT_OF_MEMORY = 2, /* host or device allocation failed */
+    DEDISP_ERR_DEVICE = 3,        /* a HIP call failed (no device, launch or fault) */
+    DEDISP_ERR_AGAIN = 4,         /* not admitted now (memory budget or slots); retry later */
+    DEDISP_ERR_NOT_FOUND = 5,     /* unknown ticket or beam */
+    DEDISP_ERR_INTERNAL = 6       /* a library invariant failed */
+};
+
+/* Human-readable name of a status code (static storage, never NULL). */
+const char *dedisp_status_string(int status);
+
+/* ---------------------------------------------------------------- plans -- */
+
+/*
+ * Build a plan: the binary64 delay table of every (channel, trial) pair,
+ * section "Searching for radio transients" (the quadratic cold-plasma delay,
+ * governed by DM alone, removed channel by channel before integrating over
+ * frequency).
+ *   nchans    >= 1 channels; channel c is centred at f_top_mhz - c*df_mhz
+ *   f_top_mhz > 0, df_mhz > 0, and the lowest channel f_top - (nchans-1)*df > 0
+ *   tsamp_s   > 0 sampling interval in seconds
+ *   dm_list   host array of ndm >= 1 finite, non-negative trial DMs (pc cm^-3),
+ *             any order; copied
+ *   in_dtype  one of enum dedisp_dtype
+ * Fails with DEDISP_ERR_INVALID_ARG if any of these is violated or a delay
+ * exceeds INT32_MAX.  Makes no GPU call (the device copy of the table is made
+ * on first use on each device).
+ */
+int dedisp_plan_create(int nchans, double f_top_mhz, double df_mhz, double tsamp_s,
+                       const double *dm_list, int ndm, int in_dtype, dedisp_plan *out_plan);
+
+/* Free a plan and its device tables.  NULL is accepted.  The caller must make
+ * sure no launch that uses the plan is still running. */
+int dedisp_plan_destroy(dedisp_plan plan);
+
+/* Largest entry of the delay table: input rows need nsamp + max_shift samples. */
+int dedisp_plan_max_shift(dedisp_plan plan, int32_t *out);
+
+/* Copy the delay table to host memory, layout [nchans][ndm] int32. */
+int dedisp_plan_shift_table(dedisp_plan plan, int32_t *host_out);
+
+/* Shape of a plan: any pointer may be NULL. */
+int dedisp_plan_dims(dedisp_plan plan, int *nchans, int *ndm, int *in_dtype);
+
+/*
+ * Kernel variants.  Variant 0 is the direct kernel (one lane per output
+ * sample); variants 1..n-1 are LDS-tiled kernels of different tile shapes.
+ * All variants produce identical results.  dedisp_variant_count returns the
+ * number of variants compiled into the library; dedisp_variant_describe
+ * writes (DMs per tile, samples per tile, threads per block) of a variant.
+ * dedisp_plan_set_variant fails with DEDISP_ERR_INVALID_ARG if the variant's
+ * on-chip window does not fit this plan's delay spread.
+ */
+int dedisp_variant_count(void);
+int dedisp_variant_describe(int variant, int *dms_per_tile, int *samples_per_tile, int *threads);
+int dedisp_plan_set_variant(dedisp_plan plan, int variant);
+int dedisp_plan_get_variant(dedisp_plan plan, int *variant);
+
+/*
+ * Time every variant that fits this plan on nsamp output samples (scratch
+ * buffers of the plan's shape are allocated and freed here, on the current
+ * device) and keep the fastest.  The result is cached in memory per
+ * (shape, device) and, when the environment variable DEDISP_TUNE_CACHE names
+ * a file, in that file.  Synchronises the device.  best_ms may be NULL.
+ */
+int dedisp_autotune(dedisp_plan plan, int64_t nsamp, int *best_variant, double *best_ms);
+
+/* -------------------------------------------------------------- execute -- */
+
+/*
+ * De-disperse one block (the paper's brute-force search: every channel shifted
+ * for every trial, then integrated over frequency).
+ *   in_dev   device pointer, [nchans][nsamp + max_shift] samples of the plan's
+ *            dtype, 16-byte aligned
+ *   out_dev  device pointer, [ndm][nsamp] int32 (U8) or float32 (F16, F32)
+ *   nsamp    number of OUTPUT samples, >= 0 (0 is a no-op)
+ *   stream   hipStream_t or NULL
+ * Asynchronous.  The first call on a device uploads the delay table
+ * (synchronously, once).
+ */
+int dedisp_execute(dedisp_plan plan, const void *in_dev, void *out_dev, int64_t nsamp, void *stream);
+
+/* --------------------------------------------------------------- batches -- */
+
+/*
+ * A batch runs many independent beams (plans of any shape and dtype, each with
+ * its own output length) in ONE persistent launch, replayed from a HIP graph.
+ * Work is cut into (beam, DM tile, time tile) items, ordered longest first, and
+ * pulled by resident workgroups from an atomic counter.  Each beam's result is
+ * identical to dedisp_execute of that beam alone.
+ *   plans   nbeams plans (not owned; they must outlive the batch)
+ *   nsamps  nbeams output lengths (>= 1)
+ */
+int dedisp_batch_create(const dedisp_plan *plans, const int64_t *nsamps, int nbeams,
+                        dedisp_batch *out_batch);
+
+/* Run the batch: ins[b] / outs[b] are device pointers laid out as for
+ * dedisp_execute.  Asynchronous on stream.  The graph is built on the first
+ * call on a stream's device and re-used; new pointers are uploaded before the
+ * replay. */
+int dedisp_batch_execute(dedisp_batch batch, const void *const *ins, void *const *outs, void *stream);
+
+/* Number of work items and workgroups the batch launches (either may be NULL). */
+int dedisp_batch_info(dedisp_batch batch, int64_t *work_items, int *workgroups);
+
+int dedisp_batch_destroy(dedisp_batch batch);
+
+/* --------------------------------------------------------------- serving -- */
+
+/*
+ * A streaming server: beams send consecutive blocks as they arrive; the server
+ * keeps each beam's last max_shift input samples on the device so that block b
+ * of a beam yields the de-dispersed series for stream times
+ * [b*B - max_shift, (b+1)*B - max_shift) (B = block length; the history before
+ * the first block is zero).  Requests are admitted while the device memory
+ * they need fits hbm_budget_bytes and fewer than max_inflight are running;
+ * admitted requests from different beams run concurrently on a pool of
+ * streams.  Blocks of one beam run in submission order.
+ *
+ * The output of every block equals dedisp_execute on that beam's history plus
+ * block, alone or in any mix of beams.
+ */
+int dedisp_server_create(size_t hbm_budget_bytes, int max_inflight, dedisp_server *out_server);
+
+/* Register a beam: plan (not owned; must outlive the server) and block length
+ * B >= 1.  Allocates the beam's device history (2 x nchans x (max_shift + B)
+ * samples) against the budget: DEDISP_ERR_AGAIN if it does not fit. */
+int dedisp_server_add_beam(dedisp_server server, dedisp_plan plan, int64_t block_nsamp, int *beam_id);
+
+/*
+ * Submit the next block of a beam.
+ *   block    host or device pointer to [nchans][B] samples; must stay valid and
+ *            unchanged until the ticket is done.  Host memory should be pinned
+ *            (hipHostMalloc) for the copy to overlap.
+ *   out_dev  device pointer to [ndm][B] outputs; must stay allocated until done
+ *   ticket   receives an id for dedisp_poll
+ * DEDISP_ERR_AGAIN: not admitted (budget or slots); nothing was queued.
+ */
+int dedisp_submit(dedisp_server server, int beam_id, const void *block, void *out_dev, uint64_t *ticket);
+
+/* Query a ticket without blocking: *done = 1 when its output is ready; then
+ * *latency_s = seconds from submission to completion.  A finished ticket is
+ * reported once more after done, then forgotten (DEDISP_ERR_NOT_FOUND).  A
+ * ticket whose launch failed reports DEDISP_ERR_DEVICE. */
+int dedisp_poll(dedisp_server server, uint64_t ticket, int *done, double *latency_s);
+
+/* Block until every submitted request has finished. */
+int dedisp_server_drain(dedisp_server server);
+
+/* Latency percentiles over completed requests, and aggregate throughput in
+ * DM*channel*samples per second between the first submission and the last
+ * completion.  Pointers may be NULL. */
+int dedisp_server_stats(dedisp_server server, double *p50_s, double *p99_s, double *dm_ch_samp_per_s);
+
+/* Drain and free a server (NULL accepted).  Plans are not freed. */
+int dedisp_server_destroy(dedisp_server server);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEDISP_H */

@@ -1,0 +1,193 @@
+// Plans: argument checks, the binary64 delay table, per-device copies, and the
+// plain execute entry point.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "dedisp_internal.h"
+
+using dedisp::DeviceTables;
+
+extern "C" const char* dedisp_status_string(int status) {
+  switch (status) {
+    case DEDISP_OK: return "ok";
+    case DEDISP_ERR_INVALID_ARG: return "invalid argument";
+    case DEDISP_ERR_OUT_OF_MEMORY: return "out of memory";
+    case DEDISP_ERR_DEVICE: return "device error";
+    case DEDISP_ERR_AGAIN: return "not admitted, try again";
+    case DEDISP_ERR_NOT_FOUND: return "not found";
+    case DEDISP_ERR_INTERNAL: return "internal error";
+    default: return "unknown status";
+  }
+}
+
+extern "C" int dedisp_plan_create(int nchans, double f_top, double df, double tsamp, const double* dm_list,
+                                  int ndm, int in_dtype, dedisp_plan* out_plan) {
+  if (out_plan == nullptr || dm_list == nullptr) return DEDISP_ERR_INVALID_ARG;
+  if (nchans < 1 || ndm < 1) return DEDISP_ERR_INVALID_ARG;
+  if (!(std::isfinite(f_top) && std::isfinite(df) && std::isfinite(tsamp))) return DEDISP_ERR_INVALID_ARG;
+  if (!(f_top > 0.0 && df > 0.0 && tsamp > 0.0)) return DEDISP_ERR_INVALID_ARG;
+  if (!(f_top - static_cast<double>(nchans - 1) * df > 0.0)) return DEDISP_ERR_INVALID_ARG;
+  if (in_dtype != DEDISP_U8 && in_dtype != DEDISP_F16 && in_dtype != DEDISP_F32) return DEDISP_ERR_INVALID_ARG;
+  for (int d = 0; d < ndm; ++d)
+    if (!std::isfinite(dm_list[d]) || dm_list[d] < 0.0) return DEDISP_ERR_INVALID_ARG;
+  // padded rows and the int32 index arithmetic of the kernels
+  if (static_cast<int64_t>(ndm) > (1 << 30)) return DEDISP_ERR_INVALID_ARG;
+
+  dedisp_plan p = new (std::nothrow) dedisp_plan_s();
+  if (p == nullptr) return DEDISP_ERR_OUT_OF_MEMORY;
+  p->nchans = nchans;
+  p->ndm = ndm;
+  p->ndm_pad = (ndm + 63) / 64 * 64;
+  p->dtype = in_dtype;
+  p->f_top = f_top;
+  p->df = df;
+  p->tsamp = tsamp;
+  try {
+    p->dms.assign(dm_list, dm_list + ndm);
+    if (!dedisp::build_shift_table(nchans, f_top, df, tsamp, dm_list, ndm, &p->shift, &p->max_shift)) {
+      delete p;
+      return DEDISP_ERR_INVALID_ARG;
+    }
+  } catch (const std::bad_alloc&) {
+    delete p;
+    return DEDISP_ERR_OUT_OF_MEMORY;
+  }
+  *out_plan = p;
+  return DEDISP_OK;
+}
+
+extern "C" int dedisp_plan_destroy(dedisp_plan p) {
+  if (p == nullptr) return DEDISP_OK;
+  int dev0 = -1;
+  if (!p->dev.empty()) (void)hipGetDevice(&dev0);
+  for (auto& kv : p->dev) {
+    if (hipSetDevice(kv.first) != hipSuccess) continue;
+    if (kv.second.shift) (void)hipFree(kv.second.shift);
+    for (auto& w : kv.second.windows) (void)hipFree(w.second);
+  }
+  if (dev0 >= 0) (void)hipSetDevice(dev0);
+  delete p;
+  return DEDISP_OK;
+}
+
+extern "C" int dedisp_plan_max_shift(dedisp_plan p, int32_t* out) {
+  if (p == nullptr || out == nullptr) return DEDISP_ERR_INVALID_ARG;
+  *out = p->max_shift;
+  return DEDISP_OK;
+}
+
+extern "C" int dedisp_plan_shift_table(dedisp_plan p, int32_t* host_out) {
+  if (p == nullptr || host_out == nullptr) return DEDISP_ERR_INVALID_ARG;
+  std::memcpy(host_out, p->shift.data(), p->shift.size() * sizeof(int32_t));
+  return DEDISP_OK;
+}
+
+extern "C" int dedisp_plan_dims(dedisp_plan p, int* nchans, int* ndm, int* in_dtype) {
+  if (p == nullptr) return DEDISP_ERR_INVALID_ARG;
+  if (nchans) *nchans = p->nchans;
+  if (ndm) *ndm = p->ndm;
+  if (in_dtype) *in_dtype = p->dtype;
+  return DEDISP_OK;
+}
+
+extern "C" int dedisp_plan_set_variant(dedisp_plan p, int variant) {
+  if (p == nullptr || variant < 0 || variant >= dedisp::variant_count()) return DEDISP_ERR_INVALID_ARG;
+  if (variant > 0 && !dedisp::variant_fits(p, variant)) return DEDISP_ERR_INVALID_ARG;
+  p->variant.store(variant);
+  return DEDISP_OK;
+}
+
+extern "C" int dedisp_plan_get_variant(dedisp_plan p, int* variant) {
+  if (p == nullptr || variant == nullptr) return DEDISP_ERR_INVALID_ARG;
+  const int v = p->variant.load();
+  *variant = v >= 0 ? v : dedisp::default_variant(p);
+  return DEDISP_OK;
+}
+
+namespace dedisp {
+
+const std::vector<int2>& host_windows(dedisp_plan p, int dms_per_tile) {
+  std::lock_guard<std::mutex> g(p->mu);
+  auto it = p->host_windows.find(dms_per_tile);
+  if (it != p->host_windows.end()) return it->second;
+  const int ntiles = (p->ndm + dms_per_tile - 1) / dms_per_tile;
+  std::vector<int2> w(static_cast<size_t>(ntiles) * p->nchans);
+  for (int t = 0; t < ntiles; ++t) {
+    const int d0 = t * dms_per_tile;
+    const int d1 = std::min(p->ndm, d0 + dms_per_tile);
+    for (int c = 0; c < p->nchans; ++c) {
+      const int32_t* row = p->shift.data() + static_cast<size_t>(c) * p->ndm;
+      int lo = row[d0], hi = row[d0];
+      for (int d = d0 + 1; d < d1; ++d) {
+        lo = std::min(lo, row[d]);
+        hi = std::max(hi, row[d]);
+      }
+      w[static_cast<size_t>(t) * p->nchans + c] = make_int2(lo, hi);
+    }
+  }
+  return p->host_windows.emplace(dms_per_tile, std::move(w)).first->second;
+}
+
+int device_tables(dedisp_plan p, int device, DeviceTables** out) {
+  std::lock_guard<std::mutex> g(p->mu);
+  DeviceTables& t = p->dev[device];
+  if (t.shift == nullptr) {
+    // Rows padded to a multiple of 64 trials, pad entries repeat the last trial
+    // so that every padded read stays inside the window of its tile.
+    std::vector<int32_t> padded(static_cast<size_t>(p->nchans) * p->ndm_pad);
+    for (int c = 0; c < p->nchans; ++c) {
+      const int32_t* src = p->shift.data() + static_cast<size_t>(c) * p->ndm;
+      int32_t* dst = padded.data() + static_cast<size_t>(c) * p->ndm_pad;
+      std::memcpy(dst, src, sizeof(int32_t) * p->ndm);
+      for (int d = p->ndm; d < p->ndm_pad; ++d) dst[d] = src[p->ndm - 1];
+    }
+    int32_t* dptr = nullptr;
+    hipError_t e = hipMalloc(&dptr, padded.size() * sizeof(int32_t));
+    if (e != hipSuccess) return hip_status(e);
+    e = hipMemcpy(dptr, padded.data(), padded.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(dptr);
+      return hip_status(e);
+    }
+    t.shift = dptr;
+  }
+  *out = &t;
+  return DEDISP_OK;
+}
+
+int device_windows(dedisp_plan p, int device, int dms_per_tile, const int2** out) {
+  const std::vector<int2>& hw = host_windows(p, dms_per_tile);
+  std::lock_guard<std::mutex> g(p->mu);
+  DeviceTables& t = p->dev[device];
+  auto it = t.windows.find(dms_per_tile);
+  if (it == t.windows.end()) {
+    int2* dptr = nullptr;
+    hipError_t e = hipMalloc(&dptr, hw.size() * sizeof(int2));
+    if (e != hipSuccess) return hip_status(e);
+    e = hipMemcpy(dptr, hw.data(), hw.size() * sizeof(int2), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(dptr);
+      return hip_status(e);
+    }
+    it = t.windows.emplace(dms_per_tile, dptr).first;
+  }
+  *out = it->second;
+  return DEDISP_OK;
+}
+
+}  // namespace dedisp
+
+extern "C" int dedisp_execute(dedisp_plan p, const void* in, void* out, int64_t nsamp, void* stream) {
+  if (p == nullptr || nsamp < 0) return DEDISP_ERR_INVALID_ARG;
+  if (nsamp == 0) return DEDISP_OK;
+  if (in == nullptr || out == nullptr) return DEDISP_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(in) & 15) != 0 || (reinterpret_cast<uintptr_t>(out) & 3) != 0)
+    return DEDISP_ERR_INVALID_ARG;
+  if (nsamp > static_cast<int64_t>(INT32_MAX) - p->max_shift) return DEDISP_ERR_INVALID_ARG;
+  int v = p->variant.load();
+  if (v < 0) v = dedisp::default_variant(p);
+  return dedisp::launch(p, v, in, out, nsamp, static_cast<hipStream_t>(stream));
+}

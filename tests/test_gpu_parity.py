@@ -1,0 +1,183 @@
+"""GPU parity: the HIP kernels against the oracle, element by element.
+
+Integer (uint8 -> int32) results must be bit-exact; float results within
+|y - y64| <= 1e-5 * sum_c |x_c| per output.  Every kernel variant is checked,
+and all variants must agree with each other bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1111_6399_amd import workloads as wl
+
+from gpu_util import REL_TOL, abs_sum, check_float, per_dm_error, run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dd(device):
+    from paper_1111_6399_amd import dedisp
+    return dedisp
+
+
+def make_case(w: wl.Workload):
+    b = w.band
+    sh, m = oracle.shift_table(b.nchans, b.f_top, b.df, b.tsamp, w.dms)
+    x = wl.generate(w, sh, m)
+    return sh, m, x
+
+
+def all_variants(dd, plan):
+    out = [0]
+    for v in range(1, dd.dedisp_variant_count()):
+        try:
+            plan.variant = v
+            out.append(v)
+        except dd.DedispError:
+            pass
+    return out
+
+
+def test_small_f32_every_variant(dd):
+    w = wl.small_f32()
+    sh, m, x = make_case(w)
+    plan = dd.Plan.for_workload(w)
+    assert plan.max_shift == m
+    assert np.array_equal(plan.shift_table(), sh)
+    want = oracle.dedisperse(x, sh, w.nsamp)
+    scale = abs_sum(x, sh, w.nsamp)
+    first = None
+    variants = all_variants(dd, plan)
+    assert len(variants) >= 3
+    for v in variants:
+        got = run(plan, x, w.nsamp, variant=v)
+        check_float(got, want, scale)
+        if first is None:
+            first = got
+        else:
+            assert np.array_equal(got.view(np.uint32), first.view(np.uint32)), "variant %d differs" % v
+    # the planted pulse is found at its trial
+    assert np.unravel_index(np.argmax(first), first.shape) == (50, 2000)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "u8"])
+def test_lofar_shape_reduced_time(dd, dtype):
+    """Full channel and trial grid of the LOFAR-shaped beam, 3000 output samples
+    (several time tiles and a ragged tail)."""
+    w = wl.lofar(dtype, nsamp=3000)
+    sh, m, x = make_case(w)
+    plan = dd.Plan.for_workload(w)
+    rows = np.unique(np.concatenate([np.arange(0, 2048, 37), [0, 1, 2047], [p[0] for p in w.pulses]]))
+    want = oracle.dedisperse(x, sh, w.nsamp, rows=rows)
+    for v in sorted({0, plan.variant}):
+        got = run(plan, x, w.nsamp, variant=v)[rows]
+        if dtype == "u8":
+            assert got.dtype == np.int32
+            assert np.array_equal(got.astype(np.int64), want)
+        else:
+            check_float(got, want, abs_sum(x, sh, w.nsamp, rows=rows))
+            e = per_dm_error(got, want)
+            assert e.max() < REL_TOL
+
+
+def test_f16_error_against_float_data(dd):
+    """Per-trial error of the half-precision path against the binary64 oracle on the
+    original float32 data (quantisation included), reported, and the exact-input gate."""
+    w = wl.lofar("f32", nsamp=2048, ndm=256)
+    sh, m, x32 = make_case(w)
+    x16 = x32.astype(np.float16)
+    plan = dd.Plan(w.band.nchans, w.band.f_top, w.band.df, w.band.tsamp, w.dms, "f16")
+    got = run(plan, x16, w.nsamp)
+    check_float(got, oracle.dedisperse(x16, sh, w.nsamp), abs_sum(x16, sh, w.nsamp))
+    e = per_dm_error(got, oracle.dedisperse(x32, sh, w.nsamp))
+    # half has an 11-bit significand: per-sample error <= 2^-11 relative, sums of
+    # N(0,1) noise stay well inside 1e-3 of the peak
+    assert e.max() < 1e-3
+
+
+@pytest.mark.parametrize("dtype", ["f32", "u8", "f16"])
+def test_closed_forms(dd, dtype):
+    b = wl.SMALL
+    dms = wl.dm_grid(70, 0.13)
+    sh, m = oracle.shift_table(b.nchans, b.f_top, b.df, b.tsamp, dms)
+    plan = dd.Plan(b.nchans, b.f_top, b.df, b.tsamp, dms, dtype)
+    nsamp = 1500
+    npdt = {"f32": np.float32, "f16": np.float16, "u8": np.uint8}[dtype]
+    # constant input
+    v = 255 if dtype == "u8" else 0.75
+    x = np.full((b.nchans, nsamp + m), v, dtype=npdt)
+    for var in all_variants(dd, plan):
+        assert np.all(run(plan, x, nsamp, variant=var) == b.nchans * v)
+    # DM 0 is the channel sum
+    rng = np.random.default_rng(9)
+    x = rng.integers(0, 200, (b.nchans, nsamp + m)).astype(npdt)
+    got = run(plan, x, nsamp)
+    assert np.array_equal(got[0].astype(np.float64), x[:, :nsamp].astype(np.float64).sum(axis=0))
+    # planted pulse, no noise: exact peak at its trial, unique
+    x = np.zeros((b.nchans, nsamp + m), dtype=npdt)
+    wl.plant_pulses(x, sh, [(40, 700, 9 if dtype == "u8" else 3.5, 1)])
+    got = run(plan, x, nsamp)
+    peak = b.nchans * (9 if dtype == "u8" else 3.5)
+    assert got[40, 700] == peak
+    assert np.count_nonzero(got == got.max()) == 1
+    # single-channel impulse recovers the delays
+    x = np.zeros((b.nchans, nsamp + m), dtype=npdt)
+    c0, t1 = 50, 1200
+    x[c0, t1] = 1
+    got = run(plan, x, nsamp)
+    for d in range(len(dms)):
+        assert list(np.flatnonzero(got[d])) == [t1 - sh[c0, d]]
+
+
+@pytest.mark.parametrize("nchans,ndm,nsamp", [(1, 1, 1), (3, 1, 7), (1, 5, 300), (33, 17, 129), (70, 65, 2049),
+                                              (5, 200, 5000)])
+def test_edge_shapes(dd, nchans, ndm, nsamp):
+    band = wl.Band(nchans, 150.0, 0.5, 327.68e-6)
+    rng = np.random.default_rng(nchans * 1000 + ndm)
+    dms = np.sort(rng.uniform(0, 20, ndm))
+    sh, m = oracle.shift_table(band.nchans, band.f_top, band.df, band.tsamp, dms)
+    x = rng.standard_normal((nchans, nsamp + m)).astype(np.float32)
+    xu = rng.integers(0, 256, (nchans, nsamp + m)).astype(np.uint8)
+    want = oracle.dedisperse(x, sh, nsamp)
+    wantu = oracle.dedisperse(xu, sh, nsamp)
+    p = dd.Plan(nchans, band.f_top, band.df, band.tsamp, dms, "f32")
+    pu = dd.Plan(nchans, band.f_top, band.df, band.tsamp, dms, "u8")
+    for v in all_variants(dd, p):
+        check_float(run(p, x, nsamp, variant=v), want, abs_sum(x, sh, nsamp))
+    for v in all_variants(dd, pu):
+        assert np.array_equal(run(pu, xu, nsamp, variant=v).astype(np.int64), wantu)
+
+
+def test_unsorted_dm_list(dd):
+    b = wl.SMALL
+    dms = np.random.default_rng(3).permutation(wl.dm_grid(50, 0.2))
+    sh, m = oracle.shift_table(b.nchans, b.f_top, b.df, b.tsamp, dms)
+    x = np.random.default_rng(4).integers(0, 256, (b.nchans, 1000 + m)).astype(np.uint8)
+    p = dd.Plan(b.nchans, b.f_top, b.df, b.tsamp, dms, "u8")
+    want = oracle.dedisperse(x, sh, 1000)
+    for v in all_variants(dd, p):
+        assert np.array_equal(run(p, x, 1000, variant=v).astype(np.int64), want)
+
+
+def test_zero_samples_is_noop(dd):
+    import torch
+    p = dd.Plan(8, 150.0, 0.5, 327.68e-6, [0.0, 1.0], "f32")
+    out = torch.full((2, 4), 3.0, device="cuda")
+    x = torch.zeros((8, 4 + p.max_shift), device="cuda")
+    p.execute(x, out, 0)
+    torch.cuda.synchronize()
+    assert torch.all(out == 3.0)
+
+
+def test_execute_rejects_bad_pointers(dd):
+    import torch
+    p = dd.Plan(8, 150.0, 0.5, 327.68e-6, [0.0, 1.0], "f32")
+    x = torch.zeros((8, 100 + p.max_shift), device="cuda")
+    out = torch.zeros((2, 100), device="cuda")
+    with pytest.raises(dd.DedispError):
+        dd.dedisp_execute(p.handle, x.data_ptr() + 4, out.data_ptr(), 100)  # misaligned input
+    with pytest.raises(dd.DedispError):
+        dd.dedisp_execute(p.handle, 0, out.data_ptr(), 100)
+    with pytest.raises(dd.DedispError):
+        dd.dedisp_execute(p.handle, x.data_ptr(), out.data_ptr(), -1)
