@@ -60,11 +60,17 @@ def cpu_baseline(x, shift, nsamp, ndm, nchans, target_s=12.0):
     pilot = time.perf_counter() - t
     n = int(min(ndm, max(16, 16 * target_s / max(pilot, 1e-3))))
     rows = np.linspace(0, ndm - 1, n).astype(np.int32)
+    reps = 0
     t = time.perf_counter()
-    oracle.dedisperse(x, shift, nsamp, rows=rows)
-    dt = time.perf_counter() - t
-    return {"value": n * nchans * nsamp / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
-            "sample": "%d of %d trials x %d output samples x %d channels, %.1f s" % (n, ndm, nsamp, nchans, dt)}
+    while True:  # the whole grid may take less than the target: repeat it
+        oracle.dedisperse(x, shift, nsamp, rows=rows)
+        reps += 1
+        dt = time.perf_counter() - t
+        if dt >= 0.5 * target_s or reps >= 50:
+            break
+    return {"value": reps * n * nchans * nsamp / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
+            "sample": "%d x (%d of %d trials x %d output samples x %d channels), %.1f s"
+                      % (reps, n, ndm, nsamp, nchans, dt)}
 
 
 def main() -> int:
@@ -73,7 +79,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lofar-f32")
-    ap.add_argument("--variant", type=int, default=-1)
+    ap.add_argument("--variant", type=int, default=-1, help="force a kernel variant (default: autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -96,6 +102,10 @@ def main() -> int:
     log("input generated: %.2f GB" % (x.nbytes / 1e9))
     if args.variant >= 0:
         plan.variant = args.variant
+    else:
+        t = time.perf_counter()
+        v, ms = dd.dedisp_autotune(plan.handle, w.nsamp)
+        log("autotune: variant %d, %.3f ms (%.1f s)" % (v, ms, time.perf_counter() - t))
 
     dev = torch.device("cuda:0")
     xin = torch.from_numpy(x).to(dev)

@@ -27,6 +27,7 @@ SOURCES = [
     ("shift_table.cpp", "host"),
     ("plan.cpp", "hip"),
     ("kernels.hip", "hip"),
+    ("autotune.cpp", "hip"),
 ]
 
 

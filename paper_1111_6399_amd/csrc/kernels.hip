@@ -104,6 +104,132 @@ __global__ __launch_bounds__(256) void dedisp_direct(const In* __restrict__ in, 
 
 // ------------------------------------------------------------- tiled --
 
+// Raw (unconverted) staging registers: four consecutive samples plus the fifth.
+// Kept raw until they are written to LDS so that the load latency overlaps
+// the previous channel's accumulation.
+template <typename T>
+struct Raw;
+template <>
+struct Raw<float> {
+  float4 v;
+  float e;
+};
+template <>
+struct Raw<__half> {
+  uint2 v;
+  unsigned short e;
+};
+template <>
+struct Raw<uint8_t> {
+  uint32_t v;
+  uint32_t e;
+};
+
+// Staging loads go through a buffer resource that covers exactly the
+// channel's window: lanes past the window, and a window that runs past the end
+// of the input, read zeros from the range check instead of touching memory.
+// Every thread issues the same number of loads per channel whatever the
+// window length, so the compiler can count them and wait for exactly the
+// channel it is about to consume while the later channels stay in flight.
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v2i __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ __forceinline__ void load_raw(__amdgpu_buffer_rsrc_t rs, int i, Raw<T>& r) {
+  if constexpr (sizeof(T) == 4) {
+    const v4i v = __builtin_amdgcn_raw_buffer_load_b128(rs, 16 * i, 0, 0);
+    r.v = make_float4(__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z), __int_as_float(v.w));
+    r.e = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 16 * i + 16, 0, 0));
+  } else if constexpr (sizeof(T) == 2) {
+    const v2i v = __builtin_amdgcn_raw_buffer_load_b64(rs, 8 * i, 0, 0);
+    r.v = make_uint2(static_cast<uint32_t>(v.x), static_cast<uint32_t>(v.y));
+    r.e = static_cast<unsigned short>(__builtin_amdgcn_raw_buffer_load_b16(rs, 8 * i + 8, 0, 0));
+  } else {
+    r.v = static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b32(rs, 4 * i, 0, 0));
+    r.e = static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b8(rs, 4 * i + 4, 0, 0));
+  }
+}
+
+__device__ __forceinline__ float h2f(uint32_t bits) { return __half2float(__ushort_as_half(static_cast<unsigned short>(bits))); }
+
+template <typename T>
+__device__ __forceinline__ void to_float(const Raw<T>& r, float4& v, float& e) {
+  if constexpr (sizeof(T) == 4) {
+    v = r.v;
+    e = r.e;
+  } else if constexpr (sizeof(T) == 2) {
+    v = make_float4(h2f(r.v.x & 0xffffu), h2f(r.v.x >> 16), h2f(r.v.y & 0xffffu), h2f(r.v.y >> 16));
+    e = h2f(r.e);
+  } else {
+    v = make_float4(static_cast<float>(r.v & 0xffu), static_cast<float>((r.v >> 8) & 0xffu),
+                    static_cast<float>((r.v >> 16) & 0xffu), static_cast<float>(r.v >> 24));
+    e = static_cast<float>(r.e);
+  }
+}
+
+// Barrier that orders LDS traffic only: global loads issued before it stay in
+// flight (a full __syncthreads() would also wait for every outstanding global
+// load, i.e. for the prefetch of the next channels).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Block i of a launch runs on XCD i mod 8.  xcd_rank() renumbers blocks so
+// that each XCD takes one contiguous run of logical indices.
+__device__ __forceinline__ int xcd_rank(int bid, int nblocks) {
+  const int xcd = bid & 7;
+  const int idx = bid >> 3;
+  const int q = nblocks >> 3, r = nblocks & 7;
+  return xcd * q + min(xcd, r) + idx;
+}
+
+// Read-only tables are read through the constant address space so that the
+// wave-uniform reads become scalar loads (s_load): they then neither occupy
+// vector registers nor wait behind the outstanding global loads of the
+// staging pipeline.
+typedef __attribute__((address_space(4))) const int32_t cint32;
+
+struct TiledArgs {
+  const void* in;
+  int64_t pitch;  // samples per input row (nsamp + max_shift)
+  int64_t total;  // samples in the input buffer
+  void* out;
+  int64_t nsamp;
+  const int32_t* shift;  // [nchans][ndm_pad]
+  const int2* win;       // [n_dm_tiles][nchans] (min, max) delay
+  int ndm, ndm_pad, nchans;
+  int cap;  // floats per LDS copy
+  int n_dm_tiles, n_t_tiles;
+  int gd, gt;        // tiles per group along trials and time
+  int n_dm_groups;   // groups along trials
+};
+
+// Logical tile of this block.  Consecutive logical indices form groups of
+// gd trial tiles x gt time tiles; an XCD runs whole groups at a time, and the
+// windows of a group overlap (neighbouring trial tiles share the top of the
+// band, neighbouring time tiles share the delay spread at the bottom), so the
+// XCD's L2 serves most of the staging traffic.
+__device__ __forceinline__ bool tile_of(const TiledArgs& a, int& dm_tile, int& t_tile) {
+  const int l = xcd_rank(blockIdx.x, gridDim.x);
+  const int bs = a.gd * a.gt;
+  const int g = l / bs;
+  const int i = l - g * bs;
+  const int gdm = g % a.n_dm_groups;
+  const int gtm = g / a.n_dm_groups;
+  dm_tile = gdm * a.gd + i % a.gd;
+  t_tile = gtm * a.gt + i / a.gd;
+  return dm_tile < a.n_dm_tiles && t_tile < a.n_t_tiles;
+}
+
+struct Geo {
+  int64_t a0;  // first staged element (multiple of 4)
+  int mis;     // offset of the window start past a0
+  int n4;      // float4 groups staged
+  int lo;      // smallest delay of the tile at this channel
+};
+
 // Workgroup tile: WD*DW trials x WT*128*KS samples.  Wave (wd, wt) owns DW
 // trials and 128*KS samples; lane l owns samples 2l, 2l+1 (+128k).
 //
@@ -111,42 +237,54 @@ __global__ __launch_bounds__(256) void dedisp_direct(const In* __restrict__ in, 
 // LDS twice: copy0[j] = x[a0 + j] and copy1[j] = x[a0 + j + 1], both 8-byte
 // aligned, so a trial with either parity of delay reads its samples as
 // naturally aligned 64-bit pairs (misaligned 64-bit LDS reads are more than
-// an order of magnitude slower on this chip).
-//
-// Tiles are numbered so that the workgroups an XCD runs (block i runs on XCD
-// i mod 8) take consecutive trial tiles of the same time tile: their windows
-// overlap, so that XCD's L2 serves most of the staging traffic.
-__device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
-  const int xcd = bid & 7;
-  const int idx = bid >> 3;
-  const int q = nblocks >> 3, r = nblocks & 7;
-  return xcd * q + min(xcd, r) + idx;
-}
-
-template <typename In, int DW, int KS, int WD, int WT>
-__global__ __launch_bounds__(64 * WD * WT) void dedisp_tiled(
-    const In* __restrict__ in, int64_t pitch, int64_t total, void* __restrict__ out_v, int64_t nsamp, int ndm,
-    const int32_t* __restrict__ shift, int ndm_pad, int nchans, const int2* __restrict__ win, int cap,
-    int n_dm_tiles) {
+// an order of magnitude slower on this chip).  Two such buffers alternate,
+// with one barrier per channel.  The global loads run P channels ahead of
+// the accumulation, in P register sets of R float4 slots per thread.
+template <typename In, int DW, int KS, int WD, int WT, int R, int P>
+__global__ __launch_bounds__(64 * WD * WT) void dedisp_tiled(const TiledArgs a) {
   constexpr int NT = 64 * WD * WT;
   constexpr int T = 128 * KS * WT;
   extern __shared__ float4 lds4[];
-  float4* copy0_4 = lds4;
-  float4* copy1_4 = lds4 + (cap >> 2);
-  const float2* copy0_2 = reinterpret_cast<const float2*>(copy0_4);
-  const float2* copy1_2 = reinterpret_cast<const float2*>(copy1_4);
+  const In* __restrict__ in = static_cast<const In*>(a.in);
+  const int q = a.cap >> 2;  // float4 per copy
 
+  int dm_tile, t_tile;
+  if (!tile_of(a, dm_tile, t_tile)) return;  // padding block of the last group
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
   const int wd = wave % WD;
   const int wt = wave / WD;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int dm_tile = tile % n_dm_tiles;
-  const int t_tile = tile / n_dm_tiles;
   const int64_t t0 = static_cast<int64_t>(t_tile) * T;
   const int dw0 = dm_tile * (DW * WD) + wd * DW;
   const int tw = wt * 128 * KS;
+  cint32* wrow = (cint32*)(a.win) + 2 * static_cast<int64_t>(dm_tile) * a.nchans;
+  const int nchans = a.nchans;
+
+  auto geo = [&](int c) {
+    const int2 mm = make_int2(wrow[2 * c], wrow[2 * c + 1]);
+    Geo g;
+    const int64_t g0 = static_cast<int64_t>(c) * a.pitch + t0 + mm.x;
+    g.a0 = g0 & ~static_cast<int64_t>(3);
+    g.mis = static_cast<int>(g0 - g.a0);
+    g.n4 = (g.mis + T + (mm.y - mm.x) + 3) >> 2;
+    g.lo = mm.x;
+    return g;
+  };
+
+  // Global loads of one channel's window into a register set.  `live` false
+  // issues the same instructions against an empty range (they return zeros
+  // without touching memory), so that every iteration issues the same number
+  // of loads and the waits stay exact.
+  auto issue = [&](const Geo& g, Raw<In>* rs, bool live) {
+    const int64_t avail = (a.total - g.a0) * static_cast<int64_t>(sizeof(In));
+    const int64_t need = (4 * static_cast<int64_t>(g.n4) + 1) * static_cast<int64_t>(sizeof(In));
+    const int num = live ? static_cast<int>(min(avail, need)) : 0;
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<In*>(in + g.a0), 0, num, 0x00020000);
+#pragma unroll
+    for (int r = 0; r < R; ++r) load_raw(rsrc, tid + r * NT, rs[r]);
+  };
 
   float part[DW][2 * KS];
   float tot[DW][2 * KS];
@@ -158,69 +296,89 @@ __global__ __launch_bounds__(64 * WD * WT) void dedisp_tiled(
       tot[j][k] = 0.f;
     }
 
-  const int2* wrow = win + static_cast<int64_t>(dm_tile) * nchans;
-  for (int c = 0; c < nchans; ++c) {
-    const int2 mm = wrow[c];
-    const int64_t g0 = static_cast<int64_t>(c) * pitch + t0 + mm.x;
-    const int64_t a0 = g0 & ~static_cast<int64_t>(3);
-    const int mis = static_cast<int>(g0 - a0);
-    const int len = mis + T + (mm.y - mm.x);
-    const int n4 = (len + 3) >> 2;
-    __syncthreads();
-    for (int i = tid; i < n4; i += NT) {
-      float4 v;
-      float e;
-      load5(in, a0 + 4 * static_cast<int64_t>(i), total, v, e);
-      copy0_4[i] = v;
-      copy1_4[i] = make_float4(v.y, v.z, v.w, e);
-    }
-    __syncthreads();
-    const int32_t* srow = shift + static_cast<int64_t>(c) * ndm_pad + dw0;
+  Raw<In> raw[P][R];
+  Geo gq[P];
 #pragma unroll
-    for (int j = 0; j < DW; ++j) {
-      const int s = srow[j];
-      const int r = mis + (s - mm.x) + tw;
-      const float2* b = (r & 1) ? (copy1_2 + ((r - 1) >> 1)) : (copy0_2 + (r >> 1));
+  for (int u = 0; u < P; ++u) {
+    gq[u] = geo(min(u, nchans - 1));
+    issue(gq[u], raw[u], u < nchans);
+  }
+
+  for (int cb = 0; cb < nchans; cb += P) {
 #pragma unroll
-      for (int k = 0; k < KS; ++k) {
-        const float2 v = b[lane + 64 * k];
-        part[j][2 * k] += v.x;
-        part[j][2 * k + 1] += v.y;
-      }
-    }
-    if (((c + 1) % kChanBlock) == 0 || c + 1 == nchans) {
+    for (int u = 0; u < P; ++u) {
+      const int c = cb + u;
+      float4* copy0_4 = lds4 + (c & 1) * 2 * q;
+      float4* copy1_4 = copy0_4 + q;
+      const Geo g = gq[u];
+      // hand the window of channel c to LDS (past the last channel this
+      // writes zeros that nobody reads)
 #pragma unroll
-      for (int j = 0; j < DW; ++j)
-#pragma unroll
-        for (int k = 0; k < 2 * KS; ++k) {
-          tot[j][k] += part[j][k];
-          part[j][k] = 0.f;
+      for (int r = 0; r < R; ++r) {
+        const int i = tid + r * NT;
+        if (i < g.n4) {
+          float4 v;
+          float e;
+          to_float(raw[u][r], v, e);
+          copy0_4[i] = v;
+          copy1_4[i] = make_float4(v.y, v.z, v.w, e);
         }
+      }
+      gq[u] = geo(min(c + P, nchans - 1));
+      issue(gq[u], raw[u], c + P < nchans);
+      lds_barrier();
+      if (c >= nchans) continue;
+
+      const float2* copy0_2 = reinterpret_cast<const float2*>(copy0_4);
+      const float2* copy1_2 = reinterpret_cast<const float2*>(copy1_4);
+      cint32* srow = (cint32*)(a.shift) + static_cast<int64_t>(c) * a.ndm_pad + dw0;
+#pragma unroll
+      for (int j = 0; j < DW; ++j) {
+        const int s = srow[j];
+        const int rr = g.mis + (s - g.lo) + tw;
+        const float2* b = (rr & 1) ? (copy1_2 + ((rr - 1) >> 1)) : (copy0_2 + (rr >> 1));
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+          const float2 v = b[lane + 64 * k];
+          part[j][2 * k] += v.x;
+          part[j][2 * k + 1] += v.y;
+        }
+      }
+      if (((c + 1) % kChanBlock) == 0 || c + 1 == nchans) {
+#pragma unroll
+        for (int j = 0; j < DW; ++j)
+#pragma unroll
+          for (int k = 0; k < 2 * KS; ++k) {
+            tot[j][k] += part[j][k];
+            part[j][k] = 0.f;
+          }
+      }
     }
   }
 
+  const int64_t nsamp = a.nsamp;
 #pragma unroll
   for (int j = 0; j < DW; ++j) {
     const int d = dw0 + j;
-    if (d >= ndm) break;
+    if (d >= a.ndm) break;
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
       const int64_t t = t0 + tw + 2 * lane + 128 * k;
       if (t + 1 < nsamp) {
         if constexpr (sizeof(In) == 1) {
-          int32_t* o = static_cast<int32_t*>(out_v) + d * nsamp + t;
+          int32_t* o = static_cast<int32_t*>(a.out) + d * nsamp + t;
           const int2 w = make_int2(static_cast<int32_t>(tot[j][2 * k]), static_cast<int32_t>(tot[j][2 * k + 1]));
           __builtin_memcpy(o, &w, 8);
         } else {
-          float* o = static_cast<float*>(out_v) + d * nsamp + t;
+          float* o = static_cast<float*>(a.out) + d * nsamp + t;
           const float2 w = make_float2(tot[j][2 * k], tot[j][2 * k + 1]);
           __builtin_memcpy(o, &w, 8);
         }
       } else if (t < nsamp) {
         if constexpr (sizeof(In) == 1)
-          static_cast<int32_t*>(out_v)[d * nsamp + t] = static_cast<int32_t>(tot[j][2 * k]);
+          static_cast<int32_t*>(a.out)[d * nsamp + t] = static_cast<int32_t>(tot[j][2 * k]);
         else
-          static_cast<float*>(out_v)[d * nsamp + t] = tot[j][2 * k];
+          static_cast<float*>(a.out)[d * nsamp + t] = tot[j][2 * k];
       }
     }
   }
@@ -228,43 +386,47 @@ __global__ __launch_bounds__(64 * WD * WT) void dedisp_tiled(
 
 // ----------------------------------------------------------- registry --
 
-using TiledFn = void (*)(const void*, int64_t, int64_t, void*, int64_t, int, const int32_t*, int, int,
-                         const int2*, int, int);
-
 struct Variant {
   TileShape shape;
+  int r;              // staging float4 slots per thread
+  int p;              // channels of prefetch
   const void* fn[3];  // by dtype: U8, F16, F32
 };
 
-#define DEDISP_VARIANT(DW, KS, WD, WT)                                                              \
+#define DEDISP_VARIANT(DW, KS, WD, WT, R, P)                                                        \
   Variant {                                                                                        \
-    TileShape{DW, KS, WD, WT}, {                                                                   \
-      reinterpret_cast<const void*>(&dedisp_tiled<uint8_t, DW, KS, WD, WT>),                        \
-          reinterpret_cast<const void*>(&dedisp_tiled<__half, DW, KS, WD, WT>),                     \
-          reinterpret_cast<const void*>(&dedisp_tiled<float, DW, KS, WD, WT>)                       \
+    TileShape{DW, KS, WD, WT}, R, P, {                                                             \
+      reinterpret_cast<const void*>(&dedisp_tiled<uint8_t, DW, KS, WD, WT, R, P>),                  \
+          reinterpret_cast<const void*>(&dedisp_tiled<__half, DW, KS, WD, WT, R, P>),               \
+          reinterpret_cast<const void*>(&dedisp_tiled<float, DW, KS, WD, WT, R, P>)                 \
     }                                                                                              \
   }
 
 const Variant kVariants[] = {
-    DEDISP_VARIANT(4, 4, 4, 2),   // 16 trials x 1024 samples, 512 threads
-    DEDISP_VARIANT(4, 4, 8, 1),   // 32 x 512
-    DEDISP_VARIANT(4, 8, 4, 2),   // 16 x 2048
-    DEDISP_VARIANT(4, 8, 8, 1),   // 32 x 1024
-    DEDISP_VARIANT(8, 4, 4, 2),   // 32 x 1024
-    DEDISP_VARIANT(2, 8, 4, 4),   // 8 x 4096
-    DEDISP_VARIANT(4, 4, 4, 1),   // 16 x 512, 256 threads
+    DEDISP_VARIANT(2, 4, 8, 2, 2, 4),  // 16 trials x 1024 samples, 1024 threads
+    DEDISP_VARIANT(2, 4, 4, 4, 2, 4),  // 8 x 2048, 1024 threads
+    DEDISP_VARIANT(1, 8, 16, 1, 2, 4), // 16 x 1024, 1024 threads
+    DEDISP_VARIANT(2, 8, 8, 2, 1, 4),  // 16 x 2048, 1024 threads
+    DEDISP_VARIANT(4, 4, 4, 2, 4, 4),  // 16 x 1024, 512 threads
+    DEDISP_VARIANT(2, 8, 4, 2, 4, 4),  // 8 x 2048, 512 threads
+    DEDISP_VARIANT(4, 4, 8, 1, 4, 4),  // 32 x 512, 512 threads
+    DEDISP_VARIANT(2, 4, 16, 1, 2, 4), // 32 x 512, 1024 threads
 };
 constexpr int kNumTiled = sizeof(kVariants) / sizeof(kVariants[0]);
 
 constexpr size_t kMaxLds = 160 * 1024;
 
-// Floats per LDS copy a tiled variant needs for this plan, or 0 if too many.
-int lds_cap(dedisp_plan p, const TileShape& s) {
-  const std::vector<int2>& w = host_windows(p, s.dms());
+// Floats per LDS copy a tiled variant needs for this plan (4 copies live:
+// two alignments x two buffers), or 0 if the plan's delay spread is too wide
+// for the variant's LDS or staging registers.
+int lds_cap(dedisp_plan p, const Variant& v) {
+  const std::vector<int2>& w = host_windows(p, v.shape.dms());
   int spread = 0;
   for (const int2& x : w) spread = std::max(spread, x.y - x.x);
-  const int64_t cap = (static_cast<int64_t>(s.samples()) + spread + 3 + 4 + 3) / 4 * 4;
-  if (2 * cap * 4 > static_cast<int64_t>(kMaxLds)) return 0;
+  const int64_t n4 = (3 + static_cast<int64_t>(v.shape.samples()) + spread + 3) / 4;
+  if (n4 > static_cast<int64_t>(v.r) * v.shape.threads()) return 0;
+  const int64_t cap = 4 * n4;
+  if (4 * cap * 4 > static_cast<int64_t>(kMaxLds)) return 0;
   return static_cast<int>(cap);
 }
 
@@ -277,11 +439,11 @@ TileShape variant_shape(int v) { return kVariants[v - 1].shape; }
 bool variant_fits(dedisp_plan p, int v) {
   if (v == 0) return true;
   if (v < 0 || v > kNumTiled) return false;
-  return lds_cap(p, kVariants[v - 1].shape) > 0;
+  return lds_cap(p, kVariants[v - 1]) > 0;
 }
 
 int default_variant(dedisp_plan p) {
-  static const int order[] = {3, 1, 2, 4, 5, 6, 7};
+  static const int order[] = {4, 1, 3, 2, 5, 6, 7, 8};
   for (int v : order)
     if (v <= kNumTiled && variant_fits(p, v)) return v;
   return 0;
@@ -320,25 +482,42 @@ int launch(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, hipSt
   }
   if (v < 0 || v > kNumTiled) return DEDISP_ERR_INVALID_ARG;
   const Variant& var = kVariants[v - 1];
-  const int cap = lds_cap(p, var.shape);
+  const int cap = lds_cap(p, var);
   if (cap == 0) return DEDISP_ERR_INVALID_ARG;
   const int2* win = nullptr;
   st = device_windows(p, dev, var.shape.dms(), &win);
   if (st != DEDISP_OK) return st;
-  const int n_dm_tiles = (p->ndm + var.shape.dms() - 1) / var.shape.dms();
+  TiledArgs a;
+  a.in = in;
+  a.pitch = pitch;
+  a.total = total;
+  a.out = out;
+  a.nsamp = nsamp;
+  a.shift = dt->shift;
+  a.win = win;
+  a.ndm = p->ndm;
+  a.ndm_pad = p->ndm_pad;
+  a.nchans = p->nchans;
+  a.cap = cap;
+  a.n_dm_tiles = (p->ndm + var.shape.dms() - 1) / var.shape.dms();
   const int64_t n_t_tiles = (nsamp + var.shape.samples() - 1) / var.shape.samples();
-  const int64_t nblocks = n_t_tiles * n_dm_tiles;
+  if (n_t_tiles > INT32_MAX / 64) return DEDISP_ERR_INVALID_ARG;
+  a.n_t_tiles = static_cast<int>(n_t_tiles);
+  // groups of up to 8 trial tiles x 4 time tiles (one per CU of an XCD)
+  a.gd = std::min(8, a.n_dm_tiles);
+  a.gt = std::min(4, a.n_t_tiles);
+  a.n_dm_groups = (a.n_dm_tiles + a.gd - 1) / a.gd;
+  const int64_t n_groups = static_cast<int64_t>(a.n_dm_groups) * ((a.n_t_tiles + a.gt - 1) / a.gt);
+  // a multiple of 8 groups, so that every XCD's run of blocks is whole groups
+  const int64_t nblocks = (n_groups + 7) / 8 * 8 * a.gd * a.gt;
   if (nblocks > INT32_MAX) return DEDISP_ERR_INVALID_ARG;
-  const size_t lds = 2 * static_cast<size_t>(cap) * 4;
+  const size_t lds = 4 * static_cast<size_t>(cap) * 4;
   const void* fn = var.fn[p->dtype];
   if (lds > 64 * 1024) {
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kMaxLds));
     if (e != hipSuccess) return hip_status(e);
   }
-  int ndm = p->ndm, ndm_pad = p->ndm_pad, nchans = p->nchans;
-  const int32_t* sh = dt->shift;
-  void* args[] = {const_cast<void**>(&in), (void*)&pitch, (void*)&total, &out, (void*)&nsamp, &ndm,
-                  (void*)&sh, &ndm_pad, &nchans, (void*)&win, (void*)&cap, (void*)&n_dm_tiles};
+  void* args[] = {&a};
   e = hipLaunchKernel(fn, dim3(static_cast<unsigned>(nblocks)), dim3(var.shape.threads()), args, lds, s);
   return hip_status(e);
 }
