@@ -81,6 +81,8 @@ def main() -> int:
     ap.add_argument("--workload", default="lofar-f32")
     ap.add_argument("--variant", type=int, default=-1, help="force a kernel variant (default: autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, run one plain device copy of the input (for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the de-dispersion path here runs on a single device "
@@ -141,6 +143,15 @@ def main() -> int:
     esize = x.itemsize
     alg_bytes = (b.nchans * (w.nsamp + plan.max_shift) * esize + w.ndm * w.nsamp * 4
                  + b.nchans * w.ndm * 4)
+
+    if args.copy_calibration:
+        # a plain copy of known size, so that profiler byte counters can be scaled
+        buf = torch.empty_like(xin)
+        buf.copy_(xin)
+        torch.cuda.synchronize()
+        log("copy calibration: %d bytes read, %d bytes written" % (xin.numel() * xin.element_size(),
+                                                                   buf.numel() * buf.element_size()))
+        del buf
 
     # spot check of the timed output against the oracle on a few trials
     rows = np.array(sorted({0, w.ndm // 3, w.ndm - 1} | {p[0] for p in w.pulses[:2]}), dtype=np.int32)

@@ -164,8 +164,20 @@ int dedisp_batch_create(const dedisp_plan *plans, const int64_t *nsamps, int nbe
  * replay. */
 int dedisp_batch_execute(dedisp_batch batch, const void *const *ins, void *const *outs, void *stream);
 
-/* Number of work items and workgroups the batch launches (either may be NULL). */
+/* Number of work items and workgroups the batch launches (either may be NULL;
+ * both are 0 before the first execute). */
 int dedisp_batch_info(dedisp_batch batch, int64_t *work_items, int *workgroups);
+
+/* Tile variant of the persistent kernel (>= 1).  Setting it rebuilds the
+ * graph on the next execute; it synchronises the batch's device. */
+int dedisp_batch_get_variant(dedisp_batch batch, int *variant);
+int dedisp_batch_set_variant(dedisp_batch batch, int variant);
+
+/* Time the batch with every tile variant that fits any of its beams, on the
+ * given buffers, and keep the fastest.  Synchronises the stream.  The outputs
+ * are overwritten (with correct results).  best_ms may be NULL. */
+int dedisp_batch_autotune(dedisp_batch batch, const void *const *ins, void *const *outs, void *stream,
+                          int *best_variant, double *best_ms);
 
 int dedisp_batch_destroy(dedisp_batch batch);
 
@@ -202,10 +214,14 @@ int dedisp_server_add_beam(dedisp_server server, dedisp_plan plan, int64_t block
  */
 int dedisp_submit(dedisp_server server, int beam_id, const void *block, void *out_dev, uint64_t *ticket);
 
-/* Query a ticket without blocking: *done = 1 when its output is ready; then
- * *latency_s = seconds from submission to completion.  A finished ticket is
- * reported once more after done, then forgotten (DEDISP_ERR_NOT_FOUND).  A
- * ticket whose launch failed reports DEDISP_ERR_DEVICE. */
+/* Query a ticket without blocking: *done = 0 while it runs.  When it has
+ * finished, *done = 1 and *latency_s = seconds from submission to the end of
+ * its kernel (recorded on the host when the stream reached it), reported once:
+ * the ticket is then forgotten and later polls return DEDISP_ERR_NOT_FOUND.  A
+ * request whose work failed returns DEDISP_ERR_DEVICE (once) and its beam
+ * restarts from a zero history, which the stream's consumer must treat as a
+ * discontinuity.  The environment variable DEDISP_FAULT_INJECT=submit:N makes
+ * the N-th submission to a server fail that way (a test hook). */
 int dedisp_poll(dedisp_server server, uint64_t ticket, int *done, double *latency_s);
 
 /* Block until every submitted request has finished. */

@@ -28,6 +28,8 @@ SOURCES = [
     ("plan.cpp", "hip"),
     ("kernels.hip", "hip"),
     ("autotune.cpp", "hip"),
+    ("batch.cpp", "hip"),
+    ("server.cpp", "hip"),
 ]
 
 

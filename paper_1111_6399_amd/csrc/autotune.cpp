@@ -60,7 +60,7 @@ extern "C" int dedisp_autotune(dedisp_plan p, int64_t nsamp, int* best_variant, 
   if (nsamp > static_cast<int64_t>(INT32_MAX) - p->max_shift) return DEDISP_ERR_INVALID_ARG;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return dedisp::hip_status(e);
+  if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
   const std::string key = tune_key(p, nsamp, dev);
   {
     std::lock_guard<std::mutex> g(g_mu);
@@ -122,7 +122,7 @@ extern "C" int dedisp_autotune(dedisp_plan p, int64_t nsamp, int* best_variant, 
   if (s) (void)hipStreamDestroy(s);
   if (din) (void)hipFree(din);
   if (dout) (void)hipFree(dout);
-  if (e != hipSuccess) return dedisp::hip_status(e);
+  if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
   if (st != DEDISP_OK) return st;
   if (best < 0) {  // nothing tiled fits: the direct kernel
     best = 0;

@@ -41,7 +41,32 @@ struct DeviceTables {
   std::map<int, int2*> windows;  // dms-per-tile -> [ntiles][nchans]
 };
 
-struct Launch;
+// Arguments of one tiled launch (one beam); also the per-beam entry of the
+// batched launch's table.
+struct TiledArgs {
+  const void* in;
+  int64_t pitch;   // samples per input row (nsamp + max_shift)
+  int64_t total4;  // samples of the input in whole groups of 4
+  void* out;
+  int64_t nsamp;
+  const int32_t* shift;  // [nchans][ndm_pad]
+  const int32_t* win;    // [n_dm_tiles][nchans][2] (min, max) delay
+  int ndm, ndm_pad, nchans;
+  int zcap;  // floats per LDS copy (a multiple of 4)
+  int n_dm_tiles, n_t_tiles;
+  int gd, gt;       // tiles per group along trials and time
+  int n_dm_groups;  // groups along trials
+  int ntail;        // samples past total4 (0..3)
+};
+
+struct BatchArgs {
+  const TiledArgs* beams;   // [nbeams]
+  const int64_t* item_end;  // [nbeams] inclusive prefix sums of work items
+  const int* dtype;         // [nbeams]
+  int nbeams;
+  int64_t n_items;
+  unsigned long long* counter;
+};
 
 }  // namespace dedisp
 
@@ -79,10 +104,37 @@ int default_variant(dedisp_plan p);
 // Launch one plan's kernel over the whole problem.
 int launch(dedisp_plan p, int variant, const void* in, void* out, int64_t nsamp, hipStream_t s);
 
+// Arguments, LDS bytes, block count and threads of a tiled launch of variant
+// v >= 1 (device tables are created on the current device if needed).
+int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, TiledArgs* a, size_t* lds,
+               int64_t* nblocks, int* threads);
+// Everything a launch of variant v of plan p needs that must not happen inside
+// a graph capture (device tables, kernel attributes), on the current device.
+int prepare(dedisp_plan p, int v);
+// Allow a kernel more than 64 KiB of dynamic LDS (once per kernel and device).
+int allow_large_lds(const void* fn);
+// Persistent batch kernel of variant v >= 1, and the counter reset kernel.
+const void* batch_kernel(int v);
+const void* reset_kernel();
+// Work-item cost of a tiled variant for a plan (channels x trials x samples
+// per item, for ordering items longest first).
+
+
+// True when the environment variable DEDISP_TRACE is set: failing HIP calls
+// are then reported on stderr with their source line.
+bool trace_enabled();
+void trace_hip_error(hipError_t e, const char* file, int line);
+
 inline int hip_status(hipError_t e) {
   if (e == hipSuccess) return DEDISP_OK;
   if (e == hipErrorOutOfMemory) return DEDISP_ERR_OUT_OF_MEMORY;
   return DEDISP_ERR_DEVICE;
 }
+
+inline int hip_status_at(hipError_t e, const char* file, int line) {
+  if (e != hipSuccess && trace_enabled()) trace_hip_error(e, file, line);
+  return hip_status(e);
+}
+#define DEDISP_HIP_STATUS(e) ::dedisp::hip_status_at((e), __FILE__, __LINE__)
 
 }  // namespace dedisp

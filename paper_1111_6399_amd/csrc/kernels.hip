@@ -25,7 +25,11 @@
 namespace dedisp {
 namespace {
 
-// ---------------------------------------------------------------- loads --
+// Read-only tables are read through the constant address space so that the
+// wave-uniform reads become scalar loads (s_load): they then neither occupy
+// vector registers nor wait behind the outstanding vector loads of the
+// staging pipeline.
+typedef __attribute__((address_space(4))) const int32_t cint32;
 
 template <typename T>
 struct Elem;
@@ -41,34 +45,6 @@ template <>
 struct Elem<uint8_t> {
   static __device__ __forceinline__ float get(const uint8_t* p, int64_t i) { return static_cast<float>(p[i]); }
 };
-
-// Four consecutive samples starting at element i (i a multiple of 4, so the
-// vector load is naturally aligned for a 16-byte aligned buffer) plus the
-// fifth; elements at or past `total` read as zero.
-template <typename T>
-__device__ __forceinline__ void load5(const T* __restrict__ p, int64_t i, int64_t total, float4& v, float& e) {
-  if (i + 4 < total) {
-    if constexpr (sizeof(T) == 4) {
-      v = *reinterpret_cast<const float4*>(p + i);
-    } else if constexpr (sizeof(T) == 2) {
-      const uint2 raw = *reinterpret_cast<const uint2*>(p + i);
-      const __half2 lo = *reinterpret_cast<const __half2*>(&raw.x);
-      const __half2 hi = *reinterpret_cast<const __half2*>(&raw.y);
-      v = make_float4(__low2float(lo), __high2float(lo), __low2float(hi), __high2float(hi));
-    } else {
-      const uint32_t raw = *reinterpret_cast<const uint32_t*>(p + i);
-      v = make_float4(static_cast<float>(raw & 0xffu), static_cast<float>((raw >> 8) & 0xffu),
-                      static_cast<float>((raw >> 16) & 0xffu), static_cast<float>(raw >> 24));
-    }
-    e = Elem<T>::get(p, i + 4);
-  } else {
-    v.x = i < total ? Elem<T>::get(p, i) : 0.f;
-    v.y = i + 1 < total ? Elem<T>::get(p, i + 1) : 0.f;
-    v.z = i + 2 < total ? Elem<T>::get(p, i + 2) : 0.f;
-    v.w = i + 3 < total ? Elem<T>::get(p, i + 3) : 0.f;
-    e = i + 4 < total ? Elem<T>::get(p, i + 4) : 0.f;
-  }
-}
 
 // ------------------------------------------------------------ direct --
 
@@ -104,20 +80,20 @@ __global__ __launch_bounds__(256) void dedisp_direct(const In* __restrict__ in, 
 
 // ------------------------------------------------------------- tiled --
 
-// Raw (unconverted) staging registers: four consecutive samples plus the fifth.
-// Kept raw until they are written to LDS so that the load latency overlaps
-// the previous channel's accumulation.
+// Raw (unconverted) staging registers: four consecutive samples.  Kept raw
+// until they are written to LDS so that the load latency overlaps the
+// accumulation of earlier channels.
 template <typename T>
 struct Raw;
 template <>
 struct Raw<float> {
   float4 v;
-  float e;
+  float e;  // the sample after the four
 };
 template <>
 struct Raw<__half> {
   uint2 v;
-  unsigned short e;
+  uint32_t e;
 };
 template <>
 struct Raw<uint8_t> {
@@ -125,17 +101,18 @@ struct Raw<uint8_t> {
   uint32_t e;
 };
 
-// Staging loads go through a buffer resource that covers exactly the
-// channel's window: lanes past the window, and a window that runs past the end
-// of the input, read zeros from the range check instead of touching memory.
-// Every thread issues the same number of loads per channel whatever the
-// window length, so the compiler can count them and wait for exactly the
-// channel it is about to consume while the later channels stay in flight.
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v2i __attribute__((ext_vector_type(2)));
 
+// Staging loads go through a buffer resource that covers exactly the part of
+// the channel's window that lies in whole 4-sample groups of the input: lanes
+// past the window read zeros from the range check instead of touching memory.
+// Every thread issues the same number of loads per channel whatever the
+// window length, so the compiler can count them and wait for exactly the
+// channel it is about to consume while later channels stay in flight.
 template <typename T>
-__device__ __forceinline__ void load_raw(__amdgpu_buffer_rsrc_t rs, int i, Raw<T>& r) {
+__device__ __forceinline__ Raw<T> load_raw(__amdgpu_buffer_rsrc_t rs, int i) {
+  Raw<T> r;
   if constexpr (sizeof(T) == 4) {
     const v4i v = __builtin_amdgcn_raw_buffer_load_b128(rs, 16 * i, 0, 0);
     r.v = make_float4(__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z), __int_as_float(v.w));
@@ -143,33 +120,43 @@ __device__ __forceinline__ void load_raw(__amdgpu_buffer_rsrc_t rs, int i, Raw<T
   } else if constexpr (sizeof(T) == 2) {
     const v2i v = __builtin_amdgcn_raw_buffer_load_b64(rs, 8 * i, 0, 0);
     r.v = make_uint2(static_cast<uint32_t>(v.x), static_cast<uint32_t>(v.y));
-    r.e = static_cast<unsigned short>(__builtin_amdgcn_raw_buffer_load_b16(rs, 8 * i + 8, 0, 0));
+    r.e = static_cast<uint32_t>(static_cast<unsigned short>(__builtin_amdgcn_raw_buffer_load_b16(rs, 8 * i + 8, 0, 0)));
   } else {
     r.v = static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b32(rs, 4 * i, 0, 0));
     r.e = static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b8(rs, 4 * i + 4, 0, 0));
   }
+  return r;
 }
 
-__device__ __forceinline__ float h2f(uint32_t bits) { return __half2float(__ushort_as_half(static_cast<unsigned short>(bits))); }
+__device__ __forceinline__ float h2f(uint32_t bits) {
+  return __half2float(__ushort_as_half(static_cast<unsigned short>(bits)));
+}
 
 template <typename T>
-__device__ __forceinline__ void to_float(const Raw<T>& r, float4& v, float& e) {
+__device__ __forceinline__ float4 to_float(const Raw<T>& r) {
   if constexpr (sizeof(T) == 4) {
-    v = r.v;
-    e = r.e;
+    return r.v;
   } else if constexpr (sizeof(T) == 2) {
-    v = make_float4(h2f(r.v.x & 0xffffu), h2f(r.v.x >> 16), h2f(r.v.y & 0xffffu), h2f(r.v.y >> 16));
-    e = h2f(r.e);
+    return make_float4(h2f(r.v.x & 0xffffu), h2f(r.v.x >> 16), h2f(r.v.y & 0xffffu), h2f(r.v.y >> 16));
   } else {
-    v = make_float4(static_cast<float>(r.v & 0xffu), static_cast<float>((r.v >> 8) & 0xffu),
-                    static_cast<float>((r.v >> 16) & 0xffu), static_cast<float>(r.v >> 24));
-    e = static_cast<float>(r.e);
+    return make_float4(static_cast<float>(r.v & 0xffu), static_cast<float>((r.v >> 8) & 0xffu),
+                       static_cast<float>((r.v >> 16) & 0xffu), static_cast<float>(r.v >> 24));
   }
 }
 
-// Barrier that orders LDS traffic only: global loads issued before it stay in
-// flight (a full __syncthreads() would also wait for every outstanding global
-// load, i.e. for the prefetch of the next channels).
+template <typename T>
+__device__ __forceinline__ float extra_float(const Raw<T>& r) {
+  if constexpr (sizeof(T) == 4)
+    return r.e;
+  else if constexpr (sizeof(T) == 2)
+    return h2f(r.e);
+  else
+    return static_cast<float>(r.e);
+}
+
+// Barrier that orders LDS traffic only: vector loads issued before it stay in
+// flight (a full __syncthreads() would also wait for every outstanding load,
+// i.e. for the prefetch of the next channels).
 __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
@@ -185,26 +172,6 @@ __device__ __forceinline__ int xcd_rank(int bid, int nblocks) {
   return xcd * q + min(xcd, r) + idx;
 }
 
-// Read-only tables are read through the constant address space so that the
-// wave-uniform reads become scalar loads (s_load): they then neither occupy
-// vector registers nor wait behind the outstanding global loads of the
-// staging pipeline.
-typedef __attribute__((address_space(4))) const int32_t cint32;
-
-struct TiledArgs {
-  const void* in;
-  int64_t pitch;  // samples per input row (nsamp + max_shift)
-  int64_t total;  // samples in the input buffer
-  void* out;
-  int64_t nsamp;
-  const int32_t* shift;  // [nchans][ndm_pad]
-  const int2* win;       // [n_dm_tiles][nchans] (min, max) delay
-  int ndm, ndm_pad, nchans;
-  int cap;  // floats per LDS copy
-  int n_dm_tiles, n_t_tiles;
-  int gd, gt;        // tiles per group along trials and time
-  int n_dm_groups;   // groups along trials
-};
 
 // Logical tile of this block.  Consecutive logical indices form groups of
 // gd trial tiles x gt time tiles; an XCD runs whole groups at a time, and the
@@ -223,33 +190,49 @@ __device__ __forceinline__ bool tile_of(const TiledArgs& a, int& dm_tile, int& t
   return dm_tile < a.n_dm_tiles && t_tile < a.n_t_tiles;
 }
 
+// LDS byte address of a shared-memory pointer.
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return static_cast<uint32_t>(reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) const void*)p));
+}
+
+// KS naturally aligned 64-bit LDS reads, 512 bytes apart, issued back to back
+// and then waited for one by one.  Written out because the compiler would
+// otherwise pair them into two-address reads (ds_read2st64_b64), which move
+// half the bytes per cycle of single 64-bit reads on this chip.
+template <int KS>
+__device__ __forceinline__ void lds_pairs(uint32_t addr, float2 (&v)[KS]) {
+#pragma unroll
+  for (int k = 0; k < KS; ++k) asm volatile("ds_read_b64 %0, %1 offset:%2" : "=v"(v[k]) : "v"(addr), "i"(512 * k));
+#pragma unroll
+  for (int k = 0; k < KS; ++k) asm volatile("s_waitcnt lgkmcnt(%1)" : "+v"(v[k]) : "i"(KS - 1 - k));
+}
+
 struct Geo {
-  int64_t a0;  // first staged element (multiple of 4)
-  int mis;     // offset of the window start past a0
-  int n4;      // float4 groups staged
-  int lo;      // smallest delay of the tile at this channel
+  int64_t a0;  // first staged sample (multiple of 4, absolute index)
+  int off;     // window index of (lane 0, k 0) for a delay of zero
+  int n4;      // groups of 4 samples staged
 };
 
 // Workgroup tile: WD*DW trials x WT*128*KS samples.  Wave (wd, wt) owns DW
 // trials and 128*KS samples; lane l owns samples 2l, 2l+1 (+128k).
 //
 // Per channel the workgroup stages the window of input its tile needs into
-// LDS twice: copy0[j] = x[a0 + j] and copy1[j] = x[a0 + j + 1], both 8-byte
-// aligned, so a trial with either parity of delay reads its samples as
-// naturally aligned 64-bit pairs (misaligned 64-bit LDS reads are more than
-// an order of magnitude slower on this chip).  Two such buffers alternate,
-// with one barrier per channel.  The global loads run P channels ahead of
-// the accumulation, in P register sets of R float4 slots per thread.
+// LDS twice: copy0[j] = x[a0 + j] and copy1[j] = x[a0 + j + 1].  A trial
+// whose window index is even reads its pairs from copy0, an odd one from
+// copy1 -- either way as naturally aligned 64-bit reads (misaligned 64-bit
+// LDS reads are more than an order of magnitude slower on this chip), with
+// consecutive lanes on consecutive pairs (no bank conflicts); the choice and
+// the delay only enter the wave-uniform base address.  Staging writes are
+// whole 16-byte groups, also conflict free.  Two such buffers alternate, with
+// one barrier per channel.  The global loads run P channels ahead of the
+// accumulation, in P register sets of R 4-sample slots per thread.
 template <typename In, int DW, int KS, int WD, int WT, int R, int P>
-__global__ __launch_bounds__(64 * WD * WT) void dedisp_tiled(const TiledArgs a) {
+__device__ __forceinline__ void tile_body(const TiledArgs& a, int dm_tile, int t_tile) {
   constexpr int NT = 64 * WD * WT;
   constexpr int T = 128 * KS * WT;
   extern __shared__ float4 lds4[];
   const In* __restrict__ in = static_cast<const In*>(a.in);
-  const int q = a.cap >> 2;  // float4 per copy
 
-  int dm_tile, t_tile;
-  if (!tile_of(a, dm_tile, t_tile)) return;  // padding block of the last group
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
@@ -260,15 +243,25 @@ __global__ __launch_bounds__(64 * WD * WT) void dedisp_tiled(const TiledArgs a) 
   const int tw = wt * 128 * KS;
   cint32* wrow = (cint32*)(a.win) + 2 * static_cast<int64_t>(dm_tile) * a.nchans;
   const int nchans = a.nchans;
+  const int q4 = a.zcap >> 2;  // float4 groups per copy
 
-  auto geo = [&](int c) {
-    const int2 mm = make_int2(wrow[2 * c], wrow[2 * c + 1]);
+  // The last 1-3 samples of the input (past the last whole group of 4) are
+  // read once here; a window that reaches them patches them in.
+  float tail[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (k < a.ntail) tail[k] = Elem<In>::get(in, a.total4 + k);
+
+  // Window of channel c; `row` = c*pitch + t0, advanced by the caller.
+  auto geo = [&](int c, int64_t row) {
+    const int lo = wrow[2 * c];
+    const int hi = wrow[2 * c + 1];
     Geo g;
-    const int64_t g0 = static_cast<int64_t>(c) * a.pitch + t0 + mm.x;
-    g.a0 = g0 & ~static_cast<int64_t>(3);
-    g.mis = static_cast<int>(g0 - g.a0);
-    g.n4 = (g.mis + T + (mm.y - mm.x) + 3) >> 2;
-    g.lo = mm.x;
+    const int64_t w0 = row + lo;
+    g.a0 = w0 & ~static_cast<int64_t>(3);
+    const int mis = static_cast<int>(w0) & 3;
+    g.n4 = (mis + T + 3 + (hi - lo)) >> 2;
+    g.off = mis + tw - lo;
     return g;
   };
 
@@ -277,13 +270,13 @@ __global__ __launch_bounds__(64 * WD * WT) void dedisp_tiled(const TiledArgs a) 
   // without touching memory), so that every iteration issues the same number
   // of loads and the waits stay exact.
   auto issue = [&](const Geo& g, Raw<In>* rs, bool live) {
-    const int64_t avail = (a.total - g.a0) * static_cast<int64_t>(sizeof(In));
-    const int64_t need = (4 * static_cast<int64_t>(g.n4) + 1) * static_cast<int64_t>(sizeof(In));
-    const int num = live ? static_cast<int>(min(avail, need)) : 0;
+    const int64_t have = a.total4 - g.a0;
+    const int64_t want = 4 * static_cast<int64_t>(g.n4) + 4;
+    const int num = live ? static_cast<int>(min(have, want)) * static_cast<int>(sizeof(In)) : 0;
     const __amdgpu_buffer_rsrc_t rsrc =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<In*>(in + g.a0), 0, num, 0x00020000);
 #pragma unroll
-    for (int r = 0; r < R; ++r) load_raw(rsrc, tid + r * NT, rs[r]);
+    for (int r = 0; r < R; ++r) rs[r] = load_raw<In>(rsrc, tid + r * NT);
   };
 
   float part[DW][2 * KS];
@@ -298,50 +291,77 @@ __global__ __launch_bounds__(64 * WD * WT) void dedisp_tiled(const TiledArgs a) 
 
   Raw<In> raw[P][R];
   Geo gq[P];
+  int64_t row = t0;  // c*pitch + t0 of the next channel to load
 #pragma unroll
   for (int u = 0; u < P; ++u) {
-    gq[u] = geo(min(u, nchans - 1));
+    gq[u] = geo(min(u, nchans - 1), row);
     issue(gq[u], raw[u], u < nchans);
+    row += a.pitch;
   }
 
   for (int cb = 0; cb < nchans; cb += P) {
 #pragma unroll
     for (int u = 0; u < P; ++u) {
       const int c = cb + u;
-      float4* copy0_4 = lds4 + (c & 1) * 2 * q;
-      float4* copy1_4 = copy0_4 + q;
+      float4* copy0 = lds4 + (c & 1) * 2 * q4;
+      float4* copy1 = copy0 + q4;
       const Geo g = gq[u];
-      // hand the window of channel c to LDS (past the last channel this
-      // writes zeros that nobody reads)
+      // Delays of this wave's trials at channel c, read before the barrier:
+      // the barrier's wait then covers these scalar loads too, so the LDS
+      // reads below never wait behind a scalar load.
+      int sh[DW];
+      {
+        cint32* srow = (cint32*)(a.shift) + static_cast<int64_t>(min(c, nchans - 1)) * a.ndm_pad + dw0;
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int i = tid + r * NT;
-        if (i < g.n4) {
-          float4 v;
-          float e;
-          to_float(raw[u][r], v, e);
-          copy0_4[i] = v;
-          copy1_4[i] = make_float4(v.y, v.z, v.w, e);
+        for (int j = 0; j < DW; ++j) sh[j] = srow[j];
+      }
+      // Hand the window of channel c to LDS.  Past the last channel this
+      // writes zeros nobody reads.
+      if (__builtin_expect(g.a0 + 4 * static_cast<int64_t>(g.n4) + 4 <= a.total4, 1)) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int i = tid + r * NT;
+          if (i < g.n4) {
+            const float4 v = to_float(raw[u][r]);
+            copy0[i] = v;
+            copy1[i] = make_float4(v.y, v.z, v.w, extra_float(raw[u][r]));
+          }
+        }
+      } else {  // the window reaches the last, partial group of the input
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int i = tid + r * NT;
+          if (i < g.n4) {
+            const int64_t gi = g.a0 + 4 * static_cast<int64_t>(i);
+            float4 v = to_float(raw[u][r]);
+            float e = extra_float(raw[u][r]);
+            if (gi == a.total4) v = make_float4(tail[0], tail[1], tail[2], 0.f);
+            if (gi + 4 == a.total4) e = tail[0];
+            copy0[i] = v;
+            copy1[i] = make_float4(v.y, v.z, v.w, e);
+          }
         }
       }
-      gq[u] = geo(min(c + P, nchans - 1));
+      gq[u] = geo(min(c + P, nchans - 1), row);
       issue(gq[u], raw[u], c + P < nchans);
+      row += a.pitch;
       lds_barrier();
       if (c >= nchans) continue;
 
-      const float2* copy0_2 = reinterpret_cast<const float2*>(copy0_4);
-      const float2* copy1_2 = reinterpret_cast<const float2*>(copy1_4);
-      cint32* srow = (cint32*)(a.shift) + static_cast<int64_t>(c) * a.ndm_pad + dw0;
+      // Each trial's KS pairs are requested before any is added, so that
+      // each wave keeps many LDS reads in flight.
+      const uint32_t base0 = lds_addr(copy0) + 8u * lane;
+      const uint32_t base1 = lds_addr(copy1) + 8u * lane - 4u;
 #pragma unroll
       for (int j = 0; j < DW; ++j) {
-        const int s = srow[j];
-        const int rr = g.mis + (s - g.lo) + tw;
-        const float2* b = (rr & 1) ? (copy1_2 + ((rr - 1) >> 1)) : (copy0_2 + (rr >> 1));
+        const int rr = sh[j] + g.off;  // window index of lane 0's first sample
+        const uint32_t addr = ((rr & 1) ? base1 : base0) + 4u * static_cast<uint32_t>(rr);
+        float2 v[KS];
+        lds_pairs<KS>(addr, v);
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
-          const float2 v = b[lane + 64 * k];
-          part[j][2 * k] += v.x;
-          part[j][2 * k + 1] += v.y;
+          part[j][2 * k] += v[k].x;
+          part[j][2 * k + 1] += v[k].y;
         }
       }
       if (((c + 1) % kChanBlock) == 0 || c + 1 == nchans) {
@@ -364,69 +384,119 @@ __global__ __launch_bounds__(64 * WD * WT) void dedisp_tiled(const TiledArgs a) 
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
       const int64_t t = t0 + tw + 2 * lane + 128 * k;
-      if (t + 1 < nsamp) {
-        if constexpr (sizeof(In) == 1) {
-          int32_t* o = static_cast<int32_t*>(a.out) + d * nsamp + t;
-          const int2 w = make_int2(static_cast<int32_t>(tot[j][2 * k]), static_cast<int32_t>(tot[j][2 * k + 1]));
-          __builtin_memcpy(o, &w, 8);
-        } else {
-          float* o = static_cast<float*>(a.out) + d * nsamp + t;
-          const float2 w = make_float2(tot[j][2 * k], tot[j][2 * k + 1]);
-          __builtin_memcpy(o, &w, 8);
+      if constexpr (sizeof(In) == 1) {
+        int32_t* o = static_cast<int32_t*>(a.out) + d * nsamp + t;
+        if (t + 1 < nsamp) {
+          const int2 w2 = make_int2(static_cast<int32_t>(tot[j][2 * k]), static_cast<int32_t>(tot[j][2 * k + 1]));
+          __builtin_memcpy(o, &w2, 8);
+        } else if (t < nsamp) {
+          *o = static_cast<int32_t>(tot[j][2 * k]);
         }
-      } else if (t < nsamp) {
-        if constexpr (sizeof(In) == 1)
-          static_cast<int32_t*>(a.out)[d * nsamp + t] = static_cast<int32_t>(tot[j][2 * k]);
-        else
-          static_cast<float*>(a.out)[d * nsamp + t] = tot[j][2 * k];
+      } else {
+        float* o = static_cast<float*>(a.out) + d * nsamp + t;
+        if (t + 1 < nsamp) {
+          const float2 w2 = make_float2(tot[j][2 * k], tot[j][2 * k + 1]);
+          __builtin_memcpy(o, &w2, 8);
+        } else if (t < nsamp) {
+          *o = tot[j][2 * k];
+        }
       }
     }
   }
 }
 
+template <typename In, int DW, int KS, int WD, int WT, int R, int P>
+__global__ __launch_bounds__(64 * WD * WT) void dedisp_tiled(const TiledArgs a) {
+  int dm_tile, t_tile;
+  if (!tile_of(a, dm_tile, t_tile)) return;  // padding block of the last group
+  tile_body<In, DW, KS, WD, WT, R, P>(a, dm_tile, t_tile);
+}
+
+// Persistent batch kernel: resident workgroups pull (beam, trial tile, time
+// tile) items from one atomic counter until none are left.  Items are
+// numbered beam by beam, beams in order of decreasing cost per item (longest
+// items first), and inside a beam in the same groups as a single launch.
+template <int DW, int KS, int WD, int WT, int R, int P>
+__global__ __launch_bounds__(64 * WD * WT) void dedisp_batch_persistent(const BatchArgs b) {
+  __shared__ long long item_s;
+  for (;;) {
+    if (threadIdx.x == 0) item_s = static_cast<long long>(atomicAdd(b.counter, 1ull));
+    lds_barrier();
+    const long long item =
+        static_cast<long long>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(item_s)))) |
+        (static_cast<long long>(__builtin_amdgcn_readfirstlane(static_cast<int>(item_s >> 32))) << 32);
+    if (item >= b.n_items) return;
+    typedef __attribute__((address_space(4))) const int64_t cint64;
+    typedef __attribute__((address_space(4))) const TiledArgs ctargs;
+    cint64* ends = (cint64*)(b.item_end);
+    int beam = 0;
+    while (beam + 1 < b.nbeams && item >= ends[beam]) ++beam;
+    const int64_t first = beam == 0 ? 0 : ends[beam - 1];
+    TiledArgs a;
+    __builtin_memcpy(&a, (const void*)((ctargs*)(b.beams) + beam), sizeof(TiledArgs));
+    const int l = static_cast<int>(item - first);
+    const int bs = a.gd * a.gt;
+    const int g = l / bs;
+    const int i = l - g * bs;
+    const int dm_tile = (g % a.n_dm_groups) * a.gd + i % a.gd;
+    const int t_tile = (g / a.n_dm_groups) * a.gt + i / a.gd;
+    if (dm_tile < a.n_dm_tiles && t_tile < a.n_t_tiles) {
+      const int dt = ((cint32*)(b.dtype))[beam];
+      if (dt == DEDISP_F32)
+        tile_body<float, DW, KS, WD, WT, R, P>(a, dm_tile, t_tile);
+      else if (dt == DEDISP_U8)
+        tile_body<uint8_t, DW, KS, WD, WT, R, P>(a, dm_tile, t_tile);
+      else
+        tile_body<__half, DW, KS, WD, WT, R, P>(a, dm_tile, t_tile);
+    }
+    lds_barrier();  // every wave is done with this item's LDS before the next
+  }
+}
+
+__global__ void reset_counter(unsigned long long* c) { *c = 0ull; }
+
 // ----------------------------------------------------------- registry --
 
 struct Variant {
   TileShape shape;
-  int r;              // staging float4 slots per thread
+  int r;              // staging 4-sample slots per thread
   int p;              // channels of prefetch
   const void* fn[3];  // by dtype: U8, F16, F32
+  const void* batch;  // persistent batch kernel
 };
 
 #define DEDISP_VARIANT(DW, KS, WD, WT, R, P)                                                        \
   Variant {                                                                                        \
-    TileShape{DW, KS, WD, WT}, R, P, {                                                             \
-      reinterpret_cast<const void*>(&dedisp_tiled<uint8_t, DW, KS, WD, WT, R, P>),                  \
-          reinterpret_cast<const void*>(&dedisp_tiled<__half, DW, KS, WD, WT, R, P>),               \
-          reinterpret_cast<const void*>(&dedisp_tiled<float, DW, KS, WD, WT, R, P>)                 \
-    }                                                                                              \
+    TileShape{DW, KS, WD, WT}, R, P,                                                               \
+        {reinterpret_cast<const void*>(&dedisp_tiled<uint8_t, DW, KS, WD, WT, R, P>),               \
+         reinterpret_cast<const void*>(&dedisp_tiled<__half, DW, KS, WD, WT, R, P>),                \
+         reinterpret_cast<const void*>(&dedisp_tiled<float, DW, KS, WD, WT, R, P>)},                \
+        reinterpret_cast<const void*>(&dedisp_batch_persistent<DW, KS, WD, WT, R, P>)               \
   }
 
 const Variant kVariants[] = {
-    DEDISP_VARIANT(2, 4, 8, 2, 2, 4),  // 16 trials x 1024 samples, 1024 threads
-    DEDISP_VARIANT(2, 4, 4, 4, 2, 4),  // 8 x 2048, 1024 threads
-    DEDISP_VARIANT(1, 8, 16, 1, 2, 4), // 16 x 1024, 1024 threads
-    DEDISP_VARIANT(2, 8, 8, 2, 1, 4),  // 16 x 2048, 1024 threads
-    DEDISP_VARIANT(4, 4, 4, 2, 4, 4),  // 16 x 1024, 512 threads
-    DEDISP_VARIANT(2, 8, 4, 2, 4, 4),  // 8 x 2048, 512 threads
-    DEDISP_VARIANT(4, 4, 8, 1, 4, 4),  // 32 x 512, 512 threads
-    DEDISP_VARIANT(2, 4, 16, 1, 2, 4), // 32 x 512, 1024 threads
+    DEDISP_VARIANT(2, 8, 8, 2, 2, 2),   // 16 trials x 2048 samples, 1024 threads
+    DEDISP_VARIANT(2, 8, 16, 1, 2, 2),  // 32 x 1024, 1024 threads
+    DEDISP_VARIANT(2, 8, 4, 4, 2, 2),   // 8 x 4096, 1024 threads
+    DEDISP_VARIANT(4, 8, 4, 2, 4, 2),   // 16 x 2048, 512 threads
+    DEDISP_VARIANT(2, 4, 8, 2, 2, 4),   // 16 x 1024, 1024 threads
+    DEDISP_VARIANT(4, 8, 2, 4, 4, 2),   // 8 x 4096, 512 threads
 };
 constexpr int kNumTiled = sizeof(kVariants) / sizeof(kVariants[0]);
 
 constexpr size_t kMaxLds = 160 * 1024;
 
-// Floats per LDS copy a tiled variant needs for this plan (4 copies live:
-// two alignments x two buffers), or 0 if the plan's delay spread is too wide
-// for the variant's LDS or staging registers.
-int lds_cap(dedisp_plan p, const Variant& v) {
+// Floats per LDS copy a tiled variant needs for this plan (two copies x two
+// buffers live), or 0 if the plan's delay spread is too wide for the
+// variant's LDS or staging registers.
+int lds_pairs(dedisp_plan p, const Variant& v) {
   const std::vector<int2>& w = host_windows(p, v.shape.dms());
   int spread = 0;
   for (const int2& x : w) spread = std::max(spread, x.y - x.x);
   const int64_t n4 = (3 + static_cast<int64_t>(v.shape.samples()) + spread + 3) / 4;
   if (n4 > static_cast<int64_t>(v.r) * v.shape.threads()) return 0;
   const int64_t cap = 4 * n4;
-  if (4 * cap * 4 > static_cast<int64_t>(kMaxLds)) return 0;
+  if (4 * cap * 4 > static_cast<int64_t>(kMaxLds) - 256) return 0;  // 256 B for static LDS
   return static_cast<int>(cap);
 }
 
@@ -439,11 +509,11 @@ TileShape variant_shape(int v) { return kVariants[v - 1].shape; }
 bool variant_fits(dedisp_plan p, int v) {
   if (v == 0) return true;
   if (v < 0 || v > kNumTiled) return false;
-  return lds_cap(p, kVariants[v - 1]) > 0;
+  return lds_pairs(p, kVariants[v - 1]) > 0;
 }
 
 int default_variant(dedisp_plan p) {
-  static const int order[] = {4, 1, 3, 2, 5, 6, 7, 8};
+  static const int order[] = {1, 2, 3, 4, 5, 6};
   for (int v : order)
     if (v <= kNumTiled && variant_fits(p, v)) return v;
   return 0;
@@ -452,7 +522,7 @@ int default_variant(dedisp_plan p) {
 int launch(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, hipStream_t s) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return hip_status(e);
+  if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
   DeviceTables* dt = nullptr;
   int st = device_tables(p, dev, &dt);
   if (st != DEDISP_OK) return st;
@@ -478,27 +548,54 @@ int launch(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, hipSt
                            static_cast<const float*>(in), pitch, out, nsamp, dt->shift, p->ndm_pad, p->nchans,
                            tblocks);
     }
-    return hip_status(hipGetLastError());
+    return DEDISP_HIP_STATUS(hipGetLastError());
   }
-  if (v < 0 || v > kNumTiled) return DEDISP_ERR_INVALID_ARG;
+  TiledArgs a;
+  size_t lds = 0;
+  int64_t nblocks = 0;
+  int threads = 0;
+  st = tiled_args(p, v, in, out, nsamp, &a, &lds, &nblocks, &threads);
+  if (st != DEDISP_OK) return st;
+  const void* fn = kVariants[v - 1].fn[p->dtype];
+  if (lds > 64 * 1024) {
+    st = allow_large_lds(fn);
+    if (st != DEDISP_OK) return st;
+  }
+  void* args[] = {&a};
+  e = hipLaunchKernel(fn, dim3(static_cast<unsigned>(nblocks)), dim3(threads), args, lds, s);
+  return DEDISP_HIP_STATUS(e);
+}
+
+int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, TiledArgs* ap, size_t* lds_out,
+               int64_t* nblocks_out, int* threads_out) {
+  if (v < 1 || v > kNumTiled) return DEDISP_ERR_INVALID_ARG;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
+  DeviceTables* dt = nullptr;
+  int st = device_tables(p, dev, &dt);
+  if (st != DEDISP_OK) return st;
   const Variant& var = kVariants[v - 1];
-  const int cap = lds_cap(p, var);
-  if (cap == 0) return DEDISP_ERR_INVALID_ARG;
+  const int zcap = lds_pairs(p, var);
+  if (zcap == 0) return DEDISP_ERR_INVALID_ARG;
   const int2* win = nullptr;
   st = device_windows(p, dev, var.shape.dms(), &win);
   if (st != DEDISP_OK) return st;
-  TiledArgs a;
+  const int64_t pitch = nsamp + p->max_shift;
+  const int64_t total = pitch * p->nchans;
+  TiledArgs& a = *ap;
   a.in = in;
   a.pitch = pitch;
-  a.total = total;
+  a.total4 = total & ~static_cast<int64_t>(3);
+  a.ntail = static_cast<int>(total - a.total4);
   a.out = out;
   a.nsamp = nsamp;
   a.shift = dt->shift;
-  a.win = win;
+  a.win = reinterpret_cast<const int32_t*>(win);
   a.ndm = p->ndm;
   a.ndm_pad = p->ndm_pad;
   a.nchans = p->nchans;
-  a.cap = cap;
+  a.zcap = zcap;
   a.n_dm_tiles = (p->ndm + var.shape.dms() - 1) / var.shape.dms();
   const int64_t n_t_tiles = (nsamp + var.shape.samples() - 1) / var.shape.samples();
   if (n_t_tiles > INT32_MAX / 64) return DEDISP_ERR_INVALID_ARG;
@@ -511,16 +608,47 @@ int launch(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, hipSt
   // a multiple of 8 groups, so that every XCD's run of blocks is whole groups
   const int64_t nblocks = (n_groups + 7) / 8 * 8 * a.gd * a.gt;
   if (nblocks > INT32_MAX) return DEDISP_ERR_INVALID_ARG;
-  const size_t lds = 4 * static_cast<size_t>(cap) * 4;
-  const void* fn = var.fn[p->dtype];
-  if (lds > 64 * 1024) {
-    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kMaxLds));
-    if (e != hipSuccess) return hip_status(e);
-  }
-  void* args[] = {&a};
-  e = hipLaunchKernel(fn, dim3(static_cast<unsigned>(nblocks)), dim3(var.shape.threads()), args, lds, s);
-  return hip_status(e);
+  *lds_out = 4 * static_cast<size_t>(zcap) * 4;
+  *nblocks_out = nblocks;
+  *threads_out = var.shape.threads();
+  return DEDISP_OK;
 }
+
+// Lift the default 64 KiB cap on dynamic LDS for a kernel, once per process
+// and device (not a stream operation, so it is done before any graph capture
+// that launches the kernel).
+int allow_large_lds(const void* fn) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, bool> done;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
+  std::lock_guard<std::mutex> g(mu);
+  auto key = std::make_pair(fn, dev);
+  if (done.count(key)) return DEDISP_OK;
+  // the batch kernel also has a few bytes of static LDS
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kMaxLds) - 256);
+  if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
+  done[key] = true;
+  return DEDISP_OK;
+}
+
+int prepare(dedisp_plan p, int v) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
+  DeviceTables* dt = nullptr;
+  int st = device_tables(p, dev, &dt);
+  if (st != DEDISP_OK || v <= 0) return st;
+  const int2* w = nullptr;
+  st = device_windows(p, dev, variant_shape(v).dms(), &w);
+  if (st != DEDISP_OK) return st;
+  return allow_large_lds(kVariants[v - 1].fn[p->dtype]);
+}
+
+const void* batch_kernel(int v) { return (v >= 1 && v <= kNumTiled) ? kVariants[v - 1].batch : nullptr; }
+
+const void* reset_kernel() { return reinterpret_cast<const void*>(&reset_counter); }
 
 }  // namespace dedisp
 

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -108,6 +110,15 @@ extern "C" int dedisp_plan_get_variant(dedisp_plan p, int* variant) {
 }
 
 namespace dedisp {
+
+bool trace_enabled() {
+  static const bool on = std::getenv("DEDISP_TRACE") != nullptr;
+  return on;
+}
+
+void trace_hip_error(hipError_t e, const char* file, int line) {
+  std::fprintf(stderr, "[dedisp] %s:%d: %s\n", file, line, hipGetErrorString(e));
+}
 
 const std::vector<int2>& host_windows(dedisp_plan p, int dms_per_tile) {
   std::lock_guard<std::mutex> g(p->mu);

@@ -57,6 +57,9 @@ _SIGS = {
     "dedisp_batch_execute": (_i, [_p, _pp, _pp, _p]),
     "dedisp_batch_info": (_i, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i)]),
     "dedisp_batch_destroy": (_i, [_p]),
+    "dedisp_batch_get_variant": (_i, [_p, ctypes.POINTER(_i)]),
+    "dedisp_batch_set_variant": (_i, [_p, _i]),
+    "dedisp_batch_autotune": (_i, [_p, _pp, _pp, _p, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
     "dedisp_server_create": (_i, [ctypes.c_size_t, _i, _pp]),
     "dedisp_server_add_beam": (_i, [_p, _p, _i64, ctypes.POINTER(_i)]),
     "dedisp_submit": (_i, [_p, _i, _p, _p, ctypes.POINTER(_u64)]),
@@ -184,6 +187,26 @@ def dedisp_batch_info(batch: int):
     w, g = _i64(), _i()
     _check(lib.dedisp_batch_info(batch, ctypes.byref(w), ctypes.byref(g)), "dedisp_batch_info")
     return w.value, g.value
+
+
+def dedisp_batch_get_variant(batch: int) -> int:
+    v = _i()
+    _check(lib.dedisp_batch_get_variant(batch, ctypes.byref(v)), "dedisp_batch_get_variant")
+    return v.value
+
+
+def dedisp_batch_set_variant(batch: int, variant: int) -> None:
+    _check(lib.dedisp_batch_set_variant(batch, int(variant)), "dedisp_batch_set_variant")
+
+
+def dedisp_batch_autotune(batch: int, ins, outs, stream=None):
+    n = len(ins)
+    a = (ctypes.c_void_p * n)(*ins)
+    b = (ctypes.c_void_p * n)(*outs)
+    v, ms = _i(), _d()
+    _check(lib.dedisp_batch_autotune(batch, a, b, _stream(stream), ctypes.byref(v), ctypes.byref(ms)),
+           "dedisp_batch_autotune")
+    return v.value, ms.value
 
 
 def dedisp_batch_destroy(batch: int) -> None:

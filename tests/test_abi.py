@@ -1,0 +1,164 @@
+"""C-ABI checks that need no GPU: exported symbols, argument checks, and the
+binary64 delay table against the oracle (the table is built on the host)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1111_6399_amd import workloads as wl
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "dedisp.h")
+
+
+@pytest.fixture(scope="module")
+def dd():
+    from paper_1111_6399_amd import dedisp
+    return dedisp
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dedisp_\w+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(dd):
+    names = declared_functions()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(dd.lib, n), n
+    assert dd.MISSING == []
+    assert set(dd.EXPORTS) == set(names)
+
+
+def test_status_strings(dd):
+    for code in range(7):
+        s = dd.status_string(code)
+        assert s and s != "unknown status"
+    assert dd.status_string(99) == "unknown status"
+
+
+@pytest.mark.parametrize("band,ndm,step", [(wl.SMALL, 100, 0.1), (wl.LOFAR, 2048, 0.1), (wl.MEERKAT, 4096, 0.5),
+                                           (wl.Band(1024, 1712.0, 428.0 / 1024, 64e-6), 4096, 0.05),
+                                           (wl.Band(256, 1712.0, 428.0 / 256, 64e-6), 512, 0.25)])
+def test_shift_table_bit_exact(dd, band, ndm, step):
+    dms = wl.dm_grid(ndm, step)
+    p = dd.Plan(band.nchans, band.f_top, band.df, band.tsamp, dms, "u8")
+    want, m = oracle.shift_table(band.nchans, band.f_top, band.df, band.tsamp, dms)
+    got = p.shift_table()
+    assert got.dtype == np.int32 and got.shape == want.shape
+    assert np.array_equal(got, want)
+    assert p.max_shift == m
+
+
+def test_shift_table_batch_beams_bit_exact(dd):
+    for w in wl.batch_beams():
+        b = w.band
+        want, m = oracle.shift_table(b.nchans, b.f_top, b.df, b.tsamp, w.dms)
+        p = dd.Plan.for_workload(w)
+        assert np.array_equal(p.shift_table(), want) and p.max_shift == m
+
+
+def test_unsorted_dm_list_table(dd):
+    b = wl.SMALL
+    dms = np.random.default_rng(1).permutation(wl.dm_grid(80, 0.123))
+    p = dd.Plan(b.nchans, b.f_top, b.df, b.tsamp, dms, "f32")
+    want, m = oracle.shift_table(b.nchans, b.f_top, b.df, b.tsamp, dms)
+    assert np.array_equal(p.shift_table(), want) and p.max_shift == m
+
+
+BAD_PLANS = [
+    dict(nchans=0), dict(nchans=-3), dict(df=0.0), dict(df=-1.0), dict(tsamp=0.0), dict(tsamp=-1e-3),
+    dict(f_top=0.0), dict(f_top=float("nan")), dict(df=float("inf")), dict(nchans=800),
+    dict(dms=[1.0, -0.5]), dict(dms=[float("nan")]), dict(dms=[float("inf")]), dict(dtype=3), dict(dtype=-1),
+    dict(dms=[1e12]),  # a delay beyond int32
+]
+
+
+@pytest.mark.parametrize("bad", BAD_PLANS)
+def test_plan_create_rejects(dd, bad):
+    args = dict(nchans=64, f_top=150.0, df=0.1953125, tsamp=327.68e-6, dms=[0.0, 1.0], dtype=2)
+    args.update(bad)
+    dm = np.asarray(args["dms"], dtype=np.float64)
+    h = ctypes.c_void_p(12345)
+    st = dd.lib.dedisp_plan_create(args["nchans"], args["f_top"], args["df"], args["tsamp"],
+                                   dm.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(dm.size), args["dtype"],
+                                   ctypes.byref(h))
+    assert st == dd.DEDISP_ERR_INVALID_ARG
+    assert h.value == 12345  # out-parameter untouched
+
+
+def test_plan_create_null_and_empty(dd):
+    h = ctypes.c_void_p()
+    dm = np.zeros(1)
+    assert dd.lib.dedisp_plan_create(8, 150.0, 0.5, 1e-3, None, 1, 2, ctypes.byref(h)) == dd.DEDISP_ERR_INVALID_ARG
+    assert dd.lib.dedisp_plan_create(8, 150.0, 0.5, 1e-3, dm.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0, 2,
+                                     ctypes.byref(h)) == dd.DEDISP_ERR_INVALID_ARG
+    assert dd.lib.dedisp_plan_create(8, 150.0, 0.5, 1e-3, dm.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1, 2,
+                                     None) == dd.DEDISP_ERR_INVALID_ARG
+
+
+def test_null_handles(dd):
+    out = ctypes.c_int32(7)
+    assert dd.lib.dedisp_plan_max_shift(None, ctypes.byref(out)) == dd.DEDISP_ERR_INVALID_ARG
+    assert out.value == 7
+    assert dd.lib.dedisp_plan_destroy(None) == dd.DEDISP_OK
+    assert dd.lib.dedisp_batch_destroy(None) == dd.DEDISP_OK
+    assert dd.lib.dedisp_server_destroy(None) == dd.DEDISP_OK
+    assert dd.lib.dedisp_execute(None, None, None, 1, None) == dd.DEDISP_ERR_INVALID_ARG
+    assert dd.lib.dedisp_server_create(1 << 30, 4, None) == dd.DEDISP_ERR_INVALID_ARG
+    assert dd.lib.dedisp_server_create(0, 4, ctypes.byref(ctypes.c_void_p())) == dd.DEDISP_ERR_INVALID_ARG
+    assert dd.lib.dedisp_submit(None, 0, None, None, None) == dd.DEDISP_ERR_INVALID_ARG
+
+
+def test_execute_argument_checks_before_device(dd):
+    p = dd.Plan(8, 150.0, 0.5, 327.68e-6, [0.0, 1.0], "f32")
+    # zero samples is a no-op that never touches the device, even with NULL buffers
+    assert dd.lib.dedisp_execute(p.handle, None, None, 0, None) == dd.DEDISP_OK
+    assert dd.lib.dedisp_execute(p.handle, None, None, -1, None) == dd.DEDISP_ERR_INVALID_ARG
+    assert dd.lib.dedisp_execute(p.handle, None, ctypes.c_void_p(4096), 10, None) == dd.DEDISP_ERR_INVALID_ARG
+    # misaligned input (needs 16 bytes), misaligned output (needs 4)
+    assert dd.lib.dedisp_execute(p.handle, ctypes.c_void_p(4100), ctypes.c_void_p(4096), 10, None) == \
+        dd.DEDISP_ERR_INVALID_ARG
+    assert dd.lib.dedisp_execute(p.handle, ctypes.c_void_p(4096), ctypes.c_void_p(4098), 10, None) == \
+        dd.DEDISP_ERR_INVALID_ARG
+    assert dd.lib.dedisp_execute(p.handle, ctypes.c_void_p(4096), ctypes.c_void_p(4096), 1 << 31, None) == \
+        dd.DEDISP_ERR_INVALID_ARG
+
+
+def test_variants(dd):
+    n = dd.dedisp_variant_count()
+    assert n >= 3
+    for v in range(n):
+        dms, samples, threads = dd.dedisp_variant_describe(v)
+        assert dms >= 1 and samples >= 1 and threads in (256, 512, 1024)
+    with pytest.raises(dd.DedispError):
+        dd.dedisp_variant_describe(n)
+    p = dd.Plan(64, 150.0, 0.1953125, 327.68e-6, wl.dm_grid(100, 0.1), "f32")
+    assert 0 <= p.variant < n
+    p.variant = 0
+    assert p.variant == 0
+    with pytest.raises(dd.DedispError):
+        p.variant = n
+    # a delay spread no tile can stage leaves only the direct kernel
+    wide = dd.Plan(16, 150.0, 4.0, 327.68e-6, wl.dm_grid(4, 200.0), "f32")
+    assert wide.variant == 0
+    for v in range(1, n):
+        with pytest.raises(dd.DedispError):
+            wide.variant = v
+
+
+def test_batch_create_checks(dd):
+    p = dd.Plan(8, 150.0, 0.5, 327.68e-6, [0.0, 1.0], "f32")
+    for plans, ns in [([p.handle], [0]), ([p.handle], [-4]), ([None], [10])]:
+        with pytest.raises(dd.DedispError):
+            dd.dedisp_batch_create(plans, ns)
+    b = dd.dedisp_batch_create([p.handle, p.handle], [100, 200])
+    assert dd.dedisp_batch_info(b) == (0, 0)
+    assert dd.dedisp_batch_get_variant(b) >= 1
+    with pytest.raises(dd.DedispError):
+        dd.dedisp_batch_set_variant(b, 0)
+    dd.dedisp_batch_destroy(b)
