@@ -50,6 +50,33 @@ def workload(name: str):
     raise SystemExit("unknown workload %s" % name)
 
 
+def device_beam_input(w, max_shift, dev):
+    """Input of one beam of the batched mix, drawn on the device: N(0,1) from
+    torch's Philox generator seeded with the beam's seed (float32), or its
+    8-bit quantisation round(clip(64 + 16 z, 0, 255))."""
+    import torch
+    g = torch.Generator(device=dev)
+    g.manual_seed(int(w.seed))
+    z = torch.randn((w.band.nchans, w.nsamp + int(max_shift)), generator=g, device=dev, dtype=torch.float32)
+    if w.dtype == "f32":
+        return z
+    q = torch.clamp(torch.round(64.0 + 16.0 * z), 0.0, 255.0).to(torch.uint8)
+    del z
+    return q
+
+
+def spot_check(x_host, shift, nsamp, out_rows, rows, dtype):
+    """Compare output rows with the oracle on the same input (exact for uint8,
+    per-element 1e-5 of the absolute sum for float)."""
+    import oracle
+    want = oracle.dedisperse(x_host, shift, nsamp, rows=rows).astype(np.float64)
+    got = out_rows.astype(np.float64)
+    if dtype == "u8":
+        return bool(np.array_equal(got, want))
+    scale = oracle.dedisperse(np.abs(x_host.astype(np.float32)), shift, nsamp, rows=rows)
+    return bool(np.all(np.abs(got - want) <= 1e-5 * scale))
+
+
 def cpu_baseline(x, shift, nsamp, ndm, nchans, target_s=12.0):
     """Time the oracle (binary64 plain loop, OpenMP) on a bounded sample of trials."""
     import oracle
@@ -73,6 +100,276 @@ def cpu_baseline(x, shift, nsamp, ndm, nchans, target_s=12.0):
                       % (reps, n, ndm, nsamp, nchans, dt)}
 
 
+def run_batch(args) -> dict:
+    """32 uneven beams (MeerKAT half-L band, nchans 256/496/1024, 2^14..2^17
+    samples, 512..4096 trials, float32/uint8 mix) in one persistent launch
+    replayed from a HIP graph, against the same beams launched one by one on
+    one stream with each plan's own tuned variant."""
+    import torch
+
+    from paper_1111_6399_amd import dedisp as dd
+    from paper_1111_6399_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    beams = wl.batch_beams()
+    plans, ins, outs = [], [], []
+    t = time.perf_counter()
+    for w in beams:
+        p = dd.Plan.for_workload(w)
+        plans.append(p)
+        ins.append(device_beam_input(w, p.max_shift, dev))
+        odt = torch.int32 if w.dtype == "u8" else torch.float32
+        outs.append(torch.empty((w.ndm, w.nsamp), dtype=odt, device=dev))
+    torch.cuda.synchronize()
+    adds = float(sum(w.ndm * w.band.nchans * w.nsamp for w in beams))
+    in_bytes = sum(x.numel() * x.element_size() for x in ins)
+    out_bytes = sum(o.numel() * o.element_size() for o in outs)
+    log("batch: %d beams, %.3g adds, inputs %.2f GB, outputs %.2f GB (set-up %.1f s)"
+        % (len(beams), adds, in_bytes / 1e9, out_bytes / 1e9, time.perf_counter() - t))
+    ip = [x.data_ptr() for x in ins]
+    op = [o.data_ptr() for o in outs]
+    stream = torch.cuda.current_stream()
+
+    batch = dd.dedisp_batch_create([p.handle for p in plans], [w.nsamp for w in beams])
+    try:
+        t = time.perf_counter()
+        if args.variant >= 0:
+            dd.dedisp_batch_set_variant(batch, args.variant)
+            dd.dedisp_batch_execute(batch, ip, op, stream)
+        else:
+            v, ms = dd.dedisp_batch_autotune(batch, ip, op, stream)
+            log("batch autotune: variant %d, %.3f ms (%.1f s)" % (v, ms, time.perf_counter() - t))
+        for _ in range(args.warmup):
+            dd.dedisp_batch_execute(batch, ip, op, stream)
+        torch.cuda.synchronize()
+        items, groups = dd.dedisp_batch_info(batch)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            ev[i][0].record(stream)
+            dd.dedisp_batch_execute(batch, ip, op, stream)
+            ev[i][1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        batch_ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+        variant = dd.dedisp_batch_get_variant(batch)
+    finally:
+        dd.dedisp_batch_destroy(batch)
+    ms_per_step = wall * 1e3 / args.steps
+    log("batched graph: %.3f ms/step wall, %.3f ms median (variant %d, %d items, %d workgroups)"
+        % (ms_per_step, batch_ms, variant, items, groups))
+
+    # spot check: two beams, one of each dtype, a few trials each
+    ok = True
+    for dt in ("f32", "u8"):
+        b = next(i for i, w in enumerate(beams) if w.dtype == dt)
+        w = beams[b]
+        rows = np.array(sorted({0, w.ndm // 2, w.ndm - 1}), dtype=np.int32)
+        got = outs[b][torch.from_numpy(rows).long().to(dev)].cpu().numpy()
+        good = spot_check(ins[b].cpu().numpy(), plans[b].shift_table(), w.nsamp, got, rows, dt)
+        log("spot check of beam %d (%s) vs oracle: %s" % (b, dt, "ok" if good else "MISMATCH"))
+        ok = ok and good
+
+    # the plain form: one launch per beam on one stream, each plan tuned on its own
+    t = time.perf_counter()
+    for p, w in zip(plans, beams):
+        if args.variant < 0:
+            dd.dedisp_autotune(p.handle, w.nsamp)
+    log("per-beam autotune %.1f s" % (time.perf_counter() - t))
+
+    def plain():
+        for p, w, x, o in zip(plans, beams, ins, outs):
+            p.execute(x, o, w.nsamp, stream)
+
+    for _ in range(args.warmup):
+        plain()
+    torch.cuda.synchronize()
+    evp = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for i in range(args.steps):
+        evp[i][0].record(stream)
+        plain()
+        evp[i][1].record(stream)
+    torch.cuda.synchronize()
+    plain_ms = float(np.median([a.elapsed_time(b) for a, b in evp]))
+    log("plain per-beam launches: %.3f ms median" % plain_ms)
+
+    achieved = adds / (batch_ms * 1e-3) / 1e12
+    return {
+        "metric": METRIC, "value": adds / (ms_per_step * 1e-3), "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+u8", "data": "synthetic",
+        "config": {"workload": "batch-32-beams", "nbeams": len(beams), "adds": adds, "in_bytes": in_bytes,
+                   "out_bytes": out_bytes, "variant": variant, "work_items": items, "workgroups": groups},
+        "rtf": sum(w.nsamp * w.band.tsamp for w in beams) / (batch_ms * 1e-3),
+        "parity_spot_check": ok,
+        "plain_per_beam": {"ms": plain_ms, "value": adds / (plain_ms * 1e-3)},
+        "speedup_vs_plain": plain_ms / batch_ms,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TADDS, "unit": "Tadd/s",
+                     "frac": achieved / ALU_PEAK_TADDS, "traffic": None, "kernel_ms": batch_ms},
+    }
+
+
+def run_served(args) -> dict:
+    """64 MeerKAT-shaped beams (4096 channels, 4096 trials 0-2047.5, uint8),
+    blocks of 32768 samples arriving as independent per-beam Poisson
+    processes at ``--rate`` times real time in aggregate.  Latency runs from a
+    block's scheduled arrival (block already in pinned host memory) to its
+    output being complete on the device.  The same arrival schedule is then
+    replayed through the plain form: one FIFO, one stream, each block copied
+    behind its beam's history and launched on its own."""
+    import torch
+
+    from paper_1111_6399_amd import dedisp as dd
+    from paper_1111_6399_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    nbeams, B = args.beams, 32768
+    w = wl.meerkat_block(B)
+    plan = dd.Plan.for_workload(w)
+    m = plan.max_shift
+    nch, ndm = w.band.nchans, w.ndm
+    block_s = B * w.band.tsamp
+    work = float(ndm) * nch * B
+    if args.variant >= 0:
+        plan.variant = args.variant
+    else:
+        v, ms = dd.dedisp_autotune(plan.handle, B)
+        log("autotune on one block: variant %d, %.3f ms" % (v, ms))
+
+    # a pool of distinct pinned blocks, cycled through by (beam, block)
+    pool = [torch.from_numpy(wl.stream_block(5, k, 0, nch, B)).pin_memory() for k in range(args.pool)]
+    rng = np.random.default_rng(5)
+    rate = args.rate / block_s  # per beam, blocks/s
+    horizon = args.warmup_s + args.duration
+    arrivals = []
+    for b in range(nbeams):
+        t, k = 0.0, 0
+        while True:
+            t += rng.exponential(1.0 / rate)
+            if t > horizon:
+                break
+            arrivals.append((t, b, k))
+            k += 1
+    arrivals.sort()
+    log("served: %d beams, %d blocks over %.0f s (offered %.1f blocks/s = %.3g adds/s)"
+        % (nbeams, len(arrivals), horizon, len(arrivals) / horizon, work * len(arrivals) / horizon))
+
+    def replay(submit, poll_done, nslots):
+        """Drive one arrival schedule; submit(beam, blk, out) -> handle or None;
+        poll_done(handle) -> bool.  Returns latencies of blocks arriving after
+        the warm-up, the completion span and the largest backlog."""
+        outs = [torch.empty((ndm, B), dtype=torch.int32, device=dev) for _ in range(nslots)]
+        free = list(range(nslots))
+        backlog, running, lat = [], [], []
+        t_start = time.perf_counter() + 0.05
+        i, max_backlog, overload = 0, 0, False
+        first_done = last_done = None
+        while i < len(arrivals) or backlog or running:
+            now = time.perf_counter() - t_start
+            while i < len(arrivals) and arrivals[i][0] <= now:
+                backlog.append(arrivals[i])
+                i += 1
+            max_backlog = max(max_backlog, len(backlog))
+            if len(backlog) > args.max_backlog and not overload:
+                # the device cannot keep up with the offered load: stop taking
+                # arrivals, finish what was admitted, report the overload
+                overload = True
+                backlog.clear()
+                i = len(arrivals)
+            progressed = False
+            for r in list(running):
+                h, slot, arr = r
+                if poll_done(h):
+                    tdone = time.perf_counter() - t_start
+                    running.remove(r)
+                    free.append(slot)
+                    if arr[0] >= args.warmup_s:
+                        lat.append(tdone - arr[0])
+                        first_done = tdone if first_done is None else first_done
+                        last_done = tdone
+                    progressed = True
+            while backlog and free:
+                arr = backlog[0]
+                slot = free[-1]
+                h = submit(arr[1], pool[(arr[1] * 7919 + arr[2]) % len(pool)], outs[slot])
+                if h is None:
+                    break
+                backlog.pop(0)
+                free.pop()
+                running.append((h, slot, arr))
+                progressed = True
+            if not progressed:
+                time.sleep(0.0002)
+        del outs
+        return np.array(lat), (first_done, last_done), (max_backlog, overload)
+
+    def summary(lat, span, backlog, label):
+        n = lat.size
+        p50, p99 = (float(np.percentile(lat, 50)), float(np.percentile(lat, 99))) if n else (None, None)
+        thr = (n - 1) * work / max(span[1] - span[0], 1e-9) if n > 1 else None
+        log("%s: %d blocks after warm-up, p50 %.1f ms, p99 %.1f ms, %.3g adds/s, max backlog %d%s"
+            % (label, n, 1e3 * (p50 or 0), 1e3 * (p99 or 0), thr or 0, backlog[0],
+               " (OVERLOADED: arrivals stopped)" if backlog[1] else ""))
+        return {"blocks": n, "p50_s": p50, "p99_s": p99, "value": thr, "max_backlog": backlog[0],
+                "overloaded": backlog[1]}
+
+    server = dd.dedisp_server_create(int(args.budget_gb * (1 << 30)), args.inflight)
+    try:
+        bids = [dd.dedisp_server_add_beam(server, plan.handle, B) for _ in range(nbeams)]
+
+        def s_submit(beam, blk, out):
+            return dd.dedisp_submit(server, bids[beam], blk.data_ptr(), out.data_ptr())
+
+        def s_poll(tk):
+            return dd.dedisp_poll(server, tk)[0]
+
+        lat, span, backlog = replay(s_submit, s_poll, args.inflight)
+        dd.dedisp_server_drain(server)
+        p50s, p99s, rate_s = dd.dedisp_server_stats(server)
+    finally:
+        dd.dedisp_server_destroy(server)
+    served = summary(lat, span, backlog, "served")
+    served["server_p50_s"], served["server_p99_s"], served["server_rate"] = p50s, p99s, rate_s
+
+    # plain FIFO: one stream, per beam one history buffer shifted in place
+    stream = torch.cuda.Stream()
+    hist = {}
+
+    def p_submit(beam, blk, out):
+        h = hist.get(beam)
+        with torch.cuda.stream(stream):
+            if h is None:
+                h = torch.zeros((nch, m + B), dtype=torch.uint8, device=dev)
+                hist[beam] = h
+            else:
+                h[:, :m] = h[:, B:B + m].clone()
+            h[:, m:].copy_(blk, non_blocking=True)
+            plan.execute(h, out, B, stream)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        return ev
+
+    lat, span, backlog = replay(p_submit, lambda ev: ev.query(), 1)
+    torch.cuda.synchronize()
+    plain = summary(lat, span, backlog, "plain FIFO")
+    hist.clear()
+
+    value = served["value"] or 0.0
+    achieved = value / 1e12
+    return {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": served["blocks"],
+        "warmup": args.warmup_s, "ms_per_step": None if not value else work / value * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "served-meerkat", "nbeams": nbeams, "block": B, "ndm": ndm, "nchans": nch,
+                   "max_shift": m, "rate_x_realtime": args.rate, "duration_s": args.duration,
+                   "inflight": args.inflight, "variant": plan.variant},
+        "served": served, "plain_fifo": plain,
+        "rtf": None if not value else value / work * block_s,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TADDS, "unit": "Tadd/s",
+                     "frac": achieved / ALU_PEAK_TADDS, "traffic": None},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +378,14 @@ def main() -> int:
     ap.add_argument("--workload", default="lofar-f32")
     ap.add_argument("--variant", type=int, default=-1, help="force a kernel variant (default: autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--beams", type=int, default=64, help="served: number of beams")
+    ap.add_argument("--rate", type=float, default=1.5, help="served: aggregate arrival rate, x real time per beam")
+    ap.add_argument("--duration", type=float, default=60.0, help="served: measured seconds after the warm-up")
+    ap.add_argument("--warmup-s", type=float, default=10.0, help="served: warm-up seconds")
+    ap.add_argument("--inflight", type=int, default=8, help="served: requests in flight")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="served: device memory budget")
+    ap.add_argument("--pool", type=int, default=4, help="served: distinct pinned blocks cycled through")
+    ap.add_argument("--max-backlog", type=int, default=256, help="served: backlog that counts as overload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one plain device copy of the input (for HBM counter scaling)")
     args = ap.parse_args()
@@ -88,6 +393,11 @@ def main() -> int:
         print("bench.py measures one GPU only: the de-dispersion path here runs on a single device "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         return 2
+
+    if args.workload in ("batch-32", "served-meerkat"):
+        res = run_batch(args) if args.workload == "batch-32" else run_served(args)
+        print(json.dumps(res), flush=True)
+        return 0 if res.get("parity_spot_check", True) else 1
 
     import torch
 

@@ -25,11 +25,11 @@ inline size_t out_size(int) { return 4; }
 // Shape of a tiled kernel variant.
 struct TileShape {
   int dw;   // trials per wave
-  int ks;   // 64-bit LDS reads per lane per trial (2 samples each)
+  int ks;   // float input: 64-bit LDS reads per lane and trial (126*ks samples per wave)
   int wd;   // waves along the trial axis
   int wt;   // waves along the time axis
   int dms() const { return dw * wd; }
-  int samples() const { return 128 * ks * wt; }
+  int samples() const { return 126 * ks * wt; }
   int threads() const { return 64 * wd * wt; }
 };
 
@@ -52,7 +52,7 @@ struct TiledArgs {
   const int32_t* shift;  // [nchans][ndm_pad]
   const int32_t* win;    // [n_dm_tiles][nchans][2] (min, max) delay
   int ndm, ndm_pad, nchans;
-  int zcap;  // floats per LDS copy (a multiple of 4)
+  int zunits;  // 4-sample units per LDS buffer
   int n_dm_tiles, n_t_tiles;
   int gd, gt;       // tiles per group along trials and time
   int n_dm_groups;  // groups along trials

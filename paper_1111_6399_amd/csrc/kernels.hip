@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "dedisp_internal.h"
 
@@ -88,17 +89,14 @@ struct Raw;
 template <>
 struct Raw<float> {
   float4 v;
-  float e;  // the sample after the four
 };
 template <>
 struct Raw<__half> {
   uint2 v;
-  uint32_t e;
 };
 template <>
 struct Raw<uint8_t> {
   uint32_t v;
-  uint32_t e;
 };
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -116,14 +114,11 @@ __device__ __forceinline__ Raw<T> load_raw(__amdgpu_buffer_rsrc_t rs, int i) {
   if constexpr (sizeof(T) == 4) {
     const v4i v = __builtin_amdgcn_raw_buffer_load_b128(rs, 16 * i, 0, 0);
     r.v = make_float4(__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z), __int_as_float(v.w));
-    r.e = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 16 * i + 16, 0, 0));
   } else if constexpr (sizeof(T) == 2) {
     const v2i v = __builtin_amdgcn_raw_buffer_load_b64(rs, 8 * i, 0, 0);
     r.v = make_uint2(static_cast<uint32_t>(v.x), static_cast<uint32_t>(v.y));
-    r.e = static_cast<uint32_t>(static_cast<unsigned short>(__builtin_amdgcn_raw_buffer_load_b16(rs, 8 * i + 8, 0, 0)));
   } else {
     r.v = static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b32(rs, 4 * i, 0, 0));
-    r.e = static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b8(rs, 4 * i + 4, 0, 0));
   }
   return r;
 }
@@ -144,16 +139,6 @@ __device__ __forceinline__ float4 to_float(const Raw<T>& r) {
   }
 }
 
-template <typename T>
-__device__ __forceinline__ float extra_float(const Raw<T>& r) {
-  if constexpr (sizeof(T) == 4)
-    return r.e;
-  else if constexpr (sizeof(T) == 2)
-    return h2f(r.e);
-  else
-    return static_cast<float>(r.e);
-}
-
 // Barrier that orders LDS traffic only: vector loads issued before it stay in
 // flight (a full __syncthreads() would also wait for every outstanding load,
 // i.e. for the prefetch of the next channels).
@@ -171,7 +156,6 @@ __device__ __forceinline__ int xcd_rank(int bid, int nblocks) {
   const int q = nblocks >> 3, r = nblocks & 7;
   return xcd * q + min(xcd, r) + idx;
 }
-
 
 // Logical tile of this block.  Consecutive logical indices form groups of
 // gd trial tiles x gt time tiles; an XCD runs whole groups at a time, and the
@@ -195,41 +179,194 @@ __device__ __forceinline__ uint32_t lds_addr(const void* p) {
   return static_cast<uint32_t>(reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) const void*)p));
 }
 
-// KS naturally aligned 64-bit LDS reads, 512 bytes apart, issued back to back
-// and then waited for one by one.  Written out because the compiler would
-// otherwise pair them into two-address reads (ds_read2st64_b64), which move
-// half the bytes per cycle of single 64-bit reads on this chip.
-template <int KS>
-__device__ __forceinline__ void lds_pairs(uint32_t addr, float2 (&v)[KS]) {
+// ------------------------------------------------ LDS read-accumulate --
+//
+// The accumulation is written in inline assembly so that the compiler neither
+// pairs the 64-bit reads into two-address reads (half the bytes per cycle on
+// this chip) nor merges the parity paths of a trial into one block joined by
+// register copies.  Reads run one trial ahead of the adds; a wait on the LDS
+// counter then covers exactly the trial about to be consumed (LDS operations
+// complete in order, so extra outstanding ones only make the wait stricter).
+
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+
+// Lane l reads the 64-bit word at addr + 504*k (addr already holds 8*l).  One
+// read of the wave spans 512 consecutive bytes, conflict free: lanes 0-62 own
+// the first 504 bytes, lane 63 reads the first 8 bytes of the next 504-byte
+// block (the neighbour that lane 62 needs for an odd-aligned trial).
+template <int N>
+__device__ __forceinline__ void lds_reads(uint32_t addr, v2u (&v)[N]) {
 #pragma unroll
-  for (int k = 0; k < KS; ++k) asm volatile("ds_read_b64 %0, %1 offset:%2" : "=v"(v[k]) : "v"(addr), "i"(512 * k));
-#pragma unroll
-  for (int k = 0; k < KS; ++k) asm volatile("s_waitcnt lgkmcnt(%1)" : "+v"(v[k]) : "i"(KS - 1 - k));
+  for (int k = 0; k < N; ++k) asm volatile("ds_read_b64 %0, %1 offset:%2" : "=v"(v[k]) : "v"(addr), "i"(504 * k));
+}
+
+template <int N>
+__device__ __forceinline__ void lds_wait() {
+  asm volatile("s_waitcnt lgkmcnt(%0)" ::"i"(N));
+}
+
+// One trial's adds for one channel, both alignments in one assembly block
+// with a scalar branch inside (written as one block so that the two paths
+// share their accumulator registers instead of being joined by copies).
+//
+// Float: x[2k], x[2k+1] are the lane's two samples of read k.  Even window
+// position: += lo and hi word of read k.  Odd position: += hi word of read k
+// and lo word of the next lane's read k (DPP wave rotation folded into the
+// add; the halo lane 63 supplies lane 62).
+//
+// 8-bit pairs: e[] holds sums of samples (2i, 2i+1) of the lane, o[] the same
+// one sample earlier.  Position mod 4 selects the set (bit 0) and whether the
+// words are the lane's own or shifted by one word (bit 1).
+#define DD_FA(a, x) "v_add_f32 %" #a ", %" #a ", %" #x "\n\t"
+#define DD_FD(a, x) "v_add_f32_dpp %" #a ", %" #x ", %" #a " wave_rol:1 row_mask:0xf bank_mask:0xf\n\t"
+#define DD_UA(a, x) "v_add_u32 %" #a ", %" #a ", %" #x "\n\t"
+#define DD_UD(a, x) "v_add_u32_dpp %" #a ", %" #x ", %" #a " wave_rol:1 row_mask:0xf bank_mask:0xf\n\t"
+
+#define DD_F_EVEN2(a0, a1, x0, x1) DD_FA(a0, x0) DD_FA(a1, x1)
+#define DD_F_ODD2(a0, a1, x0, x1) DD_FA(a0, x1) DD_FD(a1, x0)
+#define DD_U_AL2(a0, a1, x0, x1) DD_UA(a0, x0) DD_UA(a1, x1)
+#define DD_U_SH2(a0, a1, x0, x1) DD_UA(a0, x1) DD_UD(a1, x0)
+
+#define DD_BR2(P, EVEN, ODD)                           \
+  "s_bitcmp1_b32 %" #P ", 0\n\t"                      \
+  "s_cbranch_scc1 .Ldd_odd%=\n\t" EVEN "s_branch .Ldd_end%=\n" \
+  ".Ldd_odd%=:\n\t"                                    \
+  "s_nop 1\n\t" ODD ".Ldd_end%=:"
+
+#define DD_BR4(P, A0, A2, A1, A3)                                                      \
+  "s_bitcmp1_b32 %" #P ", 0\n\t"                                                      \
+  "s_cbranch_scc1 .Ldd_o%=\n\t"                                                       \
+  "s_bitcmp1_b32 %" #P ", 1\n\t"                                                      \
+  "s_cbranch_scc1 .Ldd_2%=\n\t" A0 "s_branch .Ldd_end%=\n"                            \
+  ".Ldd_2%=:\n\t"                                                                      \
+  "s_nop 1\n\t" A2 "s_branch .Ldd_end%=\n"                                             \
+  ".Ldd_o%=:\n\t"                                                                      \
+  "s_bitcmp1_b32 %" #P ", 1\n\t"                                                      \
+  "s_cbranch_scc1 .Ldd_3%=\n\t" A1 "s_branch .Ldd_end%=\n"                            \
+  ".Ldd_3%=:\n\t"                                                                      \
+  "s_nop 1\n\t" A3 ".Ldd_end%=:"
+
+template <int N>
+struct TrialAdds;
+
+template <>
+struct TrialAdds<8> {
+  static __device__ __forceinline__ void f32(float* x, const v2u (&v)[8], int p) {
+    asm volatile(DD_BR2(32,
+                        DD_F_EVEN2(0, 1, 16, 17) DD_F_EVEN2(2, 3, 18, 19) DD_F_EVEN2(4, 5, 20, 21)
+                            DD_F_EVEN2(6, 7, 22, 23) DD_F_EVEN2(8, 9, 24, 25) DD_F_EVEN2(10, 11, 26, 27)
+                                DD_F_EVEN2(12, 13, 28, 29) DD_F_EVEN2(14, 15, 30, 31),
+                        DD_F_ODD2(0, 1, 16, 17) DD_F_ODD2(2, 3, 18, 19) DD_F_ODD2(4, 5, 20, 21)
+                            DD_F_ODD2(6, 7, 22, 23) DD_F_ODD2(8, 9, 24, 25) DD_F_ODD2(10, 11, 26, 27)
+                                DD_F_ODD2(12, 13, 28, 29) DD_F_ODD2(14, 15, 30, 31))
+                 : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]),
+                   "+v"(x[7]), "+v"(x[8]), "+v"(x[9]), "+v"(x[10]), "+v"(x[11]), "+v"(x[12]), "+v"(x[13]),
+                   "+v"(x[14]), "+v"(x[15])
+                 : "v"(v[0].x), "v"(v[0].y), "v"(v[1].x), "v"(v[1].y), "v"(v[2].x), "v"(v[2].y), "v"(v[3].x),
+                   "v"(v[3].y), "v"(v[4].x), "v"(v[4].y), "v"(v[5].x), "v"(v[5].y), "v"(v[6].x), "v"(v[6].y),
+                   "v"(v[7].x), "v"(v[7].y), "s"(p)
+                 : "scc");
+  }
+};
+
+template <>
+struct TrialAdds<4> {
+  static __device__ __forceinline__ void f32(float* x, const v2u (&v)[4], int p) {
+    asm volatile(DD_BR2(16,
+                        DD_F_EVEN2(0, 1, 8, 9) DD_F_EVEN2(2, 3, 10, 11) DD_F_EVEN2(4, 5, 12, 13)
+                            DD_F_EVEN2(6, 7, 14, 15),
+                        DD_F_ODD2(0, 1, 8, 9) DD_F_ODD2(2, 3, 10, 11) DD_F_ODD2(4, 5, 12, 13)
+                            DD_F_ODD2(6, 7, 14, 15))
+                 : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]),
+                   "+v"(x[7])
+                 : "v"(v[0].x), "v"(v[0].y), "v"(v[1].x), "v"(v[1].y), "v"(v[2].x), "v"(v[2].y), "v"(v[3].x),
+                   "v"(v[3].y), "s"(p)
+                 : "scc");
+  }
+  // e[0..7], o[0..7]
+  static __device__ __forceinline__ void u8(uint32_t* e, uint32_t* o, const v2u (&v)[4], int p) {
+    asm volatile(DD_BR4(24,
+                        DD_U_AL2(0, 1, 16, 17) DD_U_AL2(2, 3, 18, 19) DD_U_AL2(4, 5, 20, 21)
+                            DD_U_AL2(6, 7, 22, 23),
+                        DD_U_SH2(0, 1, 16, 17) DD_U_SH2(2, 3, 18, 19) DD_U_SH2(4, 5, 20, 21)
+                            DD_U_SH2(6, 7, 22, 23),
+                        DD_U_AL2(8, 9, 16, 17) DD_U_AL2(10, 11, 18, 19) DD_U_AL2(12, 13, 20, 21)
+                            DD_U_AL2(14, 15, 22, 23),
+                        DD_U_SH2(8, 9, 16, 17) DD_U_SH2(10, 11, 18, 19) DD_U_SH2(12, 13, 20, 21)
+                            DD_U_SH2(14, 15, 22, 23))
+                 : "+v"(e[0]), "+v"(e[1]), "+v"(e[2]), "+v"(e[3]), "+v"(e[4]), "+v"(e[5]), "+v"(e[6]),
+                   "+v"(e[7]), "+v"(o[0]), "+v"(o[1]), "+v"(o[2]), "+v"(o[3]), "+v"(o[4]), "+v"(o[5]),
+                   "+v"(o[6]), "+v"(o[7])
+                 : "v"(v[0].x), "v"(v[0].y), "v"(v[1].x), "v"(v[1].y), "v"(v[2].x), "v"(v[2].y), "v"(v[3].x),
+                   "v"(v[3].y), "s"(p)
+                 : "scc");
+  }
+};
+
+template <>
+struct TrialAdds<2> {
+  static __device__ __forceinline__ void f32(float* x, const v2u (&v)[2], int p) {
+    asm volatile(DD_BR2(8, DD_F_EVEN2(0, 1, 4, 5) DD_F_EVEN2(2, 3, 6, 7),
+                        DD_F_ODD2(0, 1, 4, 5) DD_F_ODD2(2, 3, 6, 7))
+                 : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3])
+                 : "v"(v[0].x), "v"(v[0].y), "v"(v[1].x), "v"(v[1].y), "s"(p)
+                 : "scc");
+  }
+  static __device__ __forceinline__ void u8(uint32_t* e, uint32_t* o, const v2u (&v)[2], int p) {
+    asm volatile(DD_BR4(12, DD_U_AL2(0, 1, 8, 9) DD_U_AL2(2, 3, 10, 11),
+                        DD_U_SH2(0, 1, 8, 9) DD_U_SH2(2, 3, 10, 11),
+                        DD_U_AL2(4, 5, 8, 9) DD_U_AL2(6, 7, 10, 11),
+                        DD_U_SH2(4, 5, 8, 9) DD_U_SH2(6, 7, 10, 11))
+                 : "+v"(e[0]), "+v"(e[1]), "+v"(e[2]), "+v"(e[3]), "+v"(o[0]), "+v"(o[1]), "+v"(o[2]), "+v"(o[3])
+                 : "v"(v[0].x), "v"(v[0].y), "v"(v[1].x), "v"(v[1].y), "s"(p)
+                 : "scc");
+  }
+};
+
+// Value of lane (l + 1) mod 64 (DPP wave rotation by one lane).
+__device__ __forceinline__ uint32_t from_next_lane(uint32_t x) {
+  return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(x), 0x134, 0xF, 0xF, false));
 }
 
 struct Geo {
-  int64_t a0;  // first staged sample (multiple of 4, absolute index)
-  int off;     // window index of (lane 0, k 0) for a delay of zero
-  int n4;      // groups of 4 samples staged
+  int64_t a0;  // first staged sample (absolute index, a multiple of 4)
+  int off;     // window index of the wave's first output sample at delay 0
+  int n4;      // 4-sample units staged
 };
 
-// Workgroup tile: WD*DW trials x WT*128*KS samples.  Wave (wd, wt) owns DW
-// trials and 128*KS samples; lane l owns samples 2l, 2l+1 (+128k).
+// Workgroup tile: WD*DW trials x WT*126*KS samples.  Wave (wd, wt) owns DW
+// trials and 126*KS consecutive samples of each.
 //
 // Per channel the workgroup stages the window of input its tile needs into
-// LDS twice: copy0[j] = x[a0 + j] and copy1[j] = x[a0 + j + 1].  A trial
-// whose window index is even reads its pairs from copy0, an odd one from
-// copy1 -- either way as naturally aligned 64-bit reads (misaligned 64-bit
-// LDS reads are more than an order of magnitude slower on this chip), with
-// consecutive lanes on consecutive pairs (no bank conflicts); the choice and
-// the delay only enter the wave-uniform base address.  Staging writes are
-// whole 16-byte groups, also conflict free.  Two such buffers alternate, with
-// one barrier per channel.  The global loads run P channels ahead of the
-// accumulation, in P register sets of R 4-sample slots per thread.
+// LDS once.  Float and half input is staged as float32 (16 bytes per 4
+// samples); 8-bit input as pairs of samples in the two 16-bit halves of a
+// word (8 bytes per 4 samples), so that one 32-bit add accumulates two
+// samples exactly (a half holds 256 channels of 255 before it could carry).
+//
+// A trial reads its samples with aligned 64-bit reads.  Lanes 0-62 own the
+// output samples; lane 63 only supplies its neighbour when the trial's window
+// position is not a multiple of the word pair (float: odd sample; 8-bit: odd
+// word).  8-bit input has a second alignment, the sample within a word: odd
+// positions accumulate into a second set of words that holds every sum one
+// sample earlier, and the two sets are combined into 32-bit totals every 256
+// channels.  The delay and the alignment only enter a wave-uniform address
+// and a uniform branch.
+//
+// Float sums: channels ascending, summed in blocks of kChanBlock into a
+// partial that is then added to the total (the same order in every variant).
+//
+// Two LDS buffers alternate with one barrier per channel; the global loads run
+// P channels ahead in P register sets of R 4-sample units per thread.
 template <typename In, int DW, int KS, int WD, int WT, int R, int P>
 __device__ __forceinline__ void tile_body(const TiledArgs& a, int dm_tile, int t_tile) {
+  constexpr bool kU8 = sizeof(In) == 1;
   constexpr int NT = 64 * WD * WT;
-  constexpr int T = 128 * KS * WT;
+  constexpr int SPW = 126 * KS;          // output samples per wave and trial
+  constexpr int T = SPW * WT;            // output samples per tile
+  constexpr int NR = kU8 ? KS / 2 : KS;  // 64-bit reads per lane and trial
+  constexpr int UB = kU8 ? 8 : 16;       // LDS bytes per 4-sample unit
+  static_assert(KS % 2 == 0, "KS must be even");
+  static_assert(NR <= 15, "the LDS wait counter holds at most 15");
   extern __shared__ float4 lds4[];
   const In* __restrict__ in = static_cast<const In*>(a.in);
 
@@ -240,19 +377,27 @@ __device__ __forceinline__ void tile_body(const TiledArgs& a, int dm_tile, int t
   const int wt = wave / WD;
   const int64_t t0 = static_cast<int64_t>(t_tile) * T;
   const int dw0 = dm_tile * (DW * WD) + wd * DW;
-  const int tw = wt * 128 * KS;
+  const int tw = wt * SPW;
   cint32* wrow = (cint32*)(a.win) + 2 * static_cast<int64_t>(dm_tile) * a.nchans;
+  cint32* srow = (cint32*)(a.shift) + dw0;
   const int nchans = a.nchans;
-  const int q4 = a.zcap >> 2;  // float4 groups per copy
+  const uint32_t buf_bytes = static_cast<uint32_t>(a.zunits) * UB;
+  const uint32_t lds0 = lds_addr(lds4);
 
   // The last 1-3 samples of the input (past the last whole group of 4) are
   // read once here; a window that reaches them patches them in.
-  float tail[3] = {0.f, 0.f, 0.f};
+  uint32_t tail[3] = {0u, 0u, 0u};
 #pragma unroll
   for (int k = 0; k < 3; ++k)
-    if (k < a.ntail) tail[k] = Elem<In>::get(in, a.total4 + k);
+    if (k < a.ntail) {
+      if constexpr (kU8)
+        tail[k] = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(in[a.total4 + k])));
+      else
+        tail[k] = static_cast<uint32_t>(
+            __builtin_amdgcn_readfirstlane(__float_as_int(Elem<In>::get(in, a.total4 + k))));
+    }
 
-  // Window of channel c; `row` = c*pitch + t0, advanced by the caller.
+  // Window of channel c; `row` = c*pitch + t0.
   auto geo = [&](int c, int64_t row) {
     const int lo = wrow[2 * c];
     const int hi = wrow[2 * c + 1];
@@ -260,7 +405,7 @@ __device__ __forceinline__ void tile_body(const TiledArgs& a, int dm_tile, int t
     const int64_t w0 = row + lo;
     g.a0 = w0 & ~static_cast<int64_t>(3);
     const int mis = static_cast<int>(w0) & 3;
-    g.n4 = (mis + T + 3 + (hi - lo)) >> 2;
+    g.n4 = (mis + (hi - lo) + (T + 7)) >> 2;
     g.off = mis + tw - lo;
     return g;
   };
@@ -271,23 +416,46 @@ __device__ __forceinline__ void tile_body(const TiledArgs& a, int dm_tile, int t
   // of loads and the waits stay exact.
   auto issue = [&](const Geo& g, Raw<In>* rs, bool live) {
     const int64_t have = a.total4 - g.a0;
-    const int64_t want = 4 * static_cast<int64_t>(g.n4) + 4;
-    const int num = live ? static_cast<int>(min(have, want)) * static_cast<int>(sizeof(In)) : 0;
+    const int want = 4 * g.n4;
+    const int n = have < want ? static_cast<int>(have) : want;
+    const int num = live ? n * static_cast<int>(sizeof(In)) : 0;
     const __amdgpu_buffer_rsrc_t rsrc =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<In*>(in + g.a0), 0, num, 0x00020000);
 #pragma unroll
     for (int r = 0; r < R; ++r) rs[r] = load_raw<In>(rsrc, tid + r * NT);
   };
 
-  float part[DW][2 * KS];
-  float tot[DW][2 * KS];
-#pragma unroll
-  for (int j = 0; j < DW; ++j)
-#pragma unroll
-    for (int k = 0; k < 2 * KS; ++k) {
-      part[j][k] = 0.f;
-      tot[j][k] = 0.f;
+  // One staged unit (4 samples) in the LDS layout of the input type.
+  auto put = [&](uint32_t boff, int i, const Raw<In>& raw, bool is_tail) {
+    if constexpr (kU8) {
+      uint32_t w = raw.v;
+      uint2 u = make_uint2((w & 0xffu) | ((w & 0xff00u) << 8), ((w >> 16) & 0xffu) | ((w >> 8) & 0xff0000u));
+      if (is_tail) u = make_uint2(tail[0] | (tail[1] << 16), tail[2]);
+      reinterpret_cast<uint2*>(reinterpret_cast<char*>(lds4) + boff)[i] = u;
+    } else {
+      float4 v = to_float(raw);
+      if (is_tail) v = make_float4(__uint_as_float(tail[0]), __uint_as_float(tail[1]), __uint_as_float(tail[2]), 0.f);
+      reinterpret_cast<float4*>(reinterpret_cast<char*>(lds4) + boff)[i] = v;
     }
+  };
+
+  // Accumulators.  Float: part (current block of channels) and tot.  8-bit:
+  // ev/od words of two 16-bit sums (od one sample earlier), and 32-bit tot.
+  constexpr int NA = 2 * NR;  // accumulator words per trial and set
+  typedef typename std::conditional<kU8, uint32_t, float>::type Acc;
+  Acc acc0[DW][NA];  // float: part; 8-bit: ev
+  Acc acc1[DW][NA];  // float: unused; 8-bit: od
+  Acc tot[DW][kU8 ? 4 * NR : NA];
+#pragma unroll
+  for (int j = 0; j < DW; ++j) {
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      acc0[j][k] = 0;
+      acc1[j][k] = 0;
+    }
+#pragma unroll
+    for (int k = 0; k < (kU8 ? 4 * NR : NA); ++k) tot[j][k] = 0;
+  }
 
   Raw<In> raw[P][R];
   Geo gq[P];
@@ -303,43 +471,30 @@ __device__ __forceinline__ void tile_body(const TiledArgs& a, int dm_tile, int t
 #pragma unroll
     for (int u = 0; u < P; ++u) {
       const int c = cb + u;
-      float4* copy0 = lds4 + (c & 1) * 2 * q4;
-      float4* copy1 = copy0 + q4;
+      const uint32_t boff = (c & 1) ? buf_bytes : 0u;
       const Geo g = gq[u];
       // Delays of this wave's trials at channel c, read before the barrier:
-      // the barrier's wait then covers these scalar loads too, so the LDS
-      // reads below never wait behind a scalar load.
+      // the barrier's wait then covers these scalar loads too.
       int sh[DW];
       {
-        cint32* srow = (cint32*)(a.shift) + static_cast<int64_t>(min(c, nchans - 1)) * a.ndm_pad + dw0;
+        cint32* sr = srow + static_cast<int64_t>(min(c, nchans - 1)) * a.ndm_pad;
 #pragma unroll
-        for (int j = 0; j < DW; ++j) sh[j] = srow[j];
+        for (int j = 0; j < DW; ++j) sh[j] = sr[j];
       }
       // Hand the window of channel c to LDS.  Past the last channel this
       // writes zeros nobody reads.
-      if (__builtin_expect(g.a0 + 4 * static_cast<int64_t>(g.n4) + 4 <= a.total4, 1)) {
+      if (__builtin_expect(g.a0 + 4 * static_cast<int64_t>(g.n4) <= a.total4, 1)) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const int i = tid + r * NT;
-          if (i < g.n4) {
-            const float4 v = to_float(raw[u][r]);
-            copy0[i] = v;
-            copy1[i] = make_float4(v.y, v.z, v.w, extra_float(raw[u][r]));
-          }
+          if (i < g.n4) put(boff, i, raw[u][r], false);
         }
       } else {  // the window reaches the last, partial group of the input
+        const int itail = static_cast<int>((a.total4 - g.a0) >> 2);  // unit holding the tail
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const int i = tid + r * NT;
-          if (i < g.n4) {
-            const int64_t gi = g.a0 + 4 * static_cast<int64_t>(i);
-            float4 v = to_float(raw[u][r]);
-            float e = extra_float(raw[u][r]);
-            if (gi == a.total4) v = make_float4(tail[0], tail[1], tail[2], 0.f);
-            if (gi + 4 == a.total4) e = tail[0];
-            copy0[i] = v;
-            copy1[i] = make_float4(v.y, v.z, v.w, e);
-          }
+          if (i < g.n4) put(boff, i, raw[u][r], i == itail);
         }
       }
       gq[u] = geo(min(c + P, nchans - 1), row);
@@ -348,51 +503,84 @@ __device__ __forceinline__ void tile_body(const TiledArgs& a, int dm_tile, int t
       lds_barrier();
       if (c >= nchans) continue;
 
-      // Each trial's KS pairs are requested before any is added, so that
-      // each wave keeps many LDS reads in flight.
-      const uint32_t base0 = lds_addr(copy0) + 8u * lane;
-      const uint32_t base1 = lds_addr(copy1) + 8u * lane - 4u;
+      const uint32_t vb = lds0 + boff + 8u * static_cast<uint32_t>(lane);
+      int pj[DW];
+#pragma unroll
+      for (int j = 0; j < DW; ++j) pj[j] = sh[j] + g.off;  // window index of the wave's first sample
+      auto addr = [&](int p) -> uint32_t {
+        return kU8 ? vb + 8u * static_cast<uint32_t>(p >> 2) : vb + 4u * static_cast<uint32_t>(p & ~1);
+      };
+      v2u rb[2][NR];
+      lds_reads<NR>(addr(pj[0]), rb[0]);
 #pragma unroll
       for (int j = 0; j < DW; ++j) {
-        const int rr = sh[j] + g.off;  // window index of lane 0's first sample
-        const uint32_t addr = ((rr & 1) ? base1 : base0) + 4u * static_cast<uint32_t>(rr);
-        float2 v[KS];
-        lds_pairs<KS>(addr, v);
-#pragma unroll
-        for (int k = 0; k < KS; ++k) {
-          part[j][2 * k] += v[k].x;
-          part[j][2 * k + 1] += v[k].y;
+        if (j + 1 < DW) {
+          lds_reads<NR>(addr(pj[j + 1]), rb[(j + 1) & 1]);
+          lds_wait<NR>();
+        } else {
+          lds_wait<0>();
         }
+        if constexpr (kU8)
+          TrialAdds<NR>::u8(acc0[j], acc1[j], rb[j & 1], pj[j]);
+        else
+          TrialAdds<NR>::f32(acc0[j], rb[j & 1], pj[j]);
       }
-      if (((c + 1) % kChanBlock) == 0 || c + 1 == nchans) {
+      if constexpr (kU8) {
+        if (((c + 1) & 255) == 0 || c + 1 == nchans) {
 #pragma unroll
-        for (int j = 0; j < DW; ++j)
+          for (int j = 0; j < DW; ++j)
 #pragma unroll
-          for (int k = 0; k < 2 * KS; ++k) {
-            tot[j][k] += part[j][k];
-            part[j][k] = 0.f;
-          }
+            for (int k = 0; k < NR; ++k) {
+              const uint32_t ex = acc0[j][2 * k], ey = acc0[j][2 * k + 1];
+              const uint32_t ox = acc1[j][2 * k], oy = acc1[j][2 * k + 1];
+              const uint32_t oxn = from_next_lane(ox);
+              tot[j][4 * k + 0] += (ex & 0xffffu) + (ox >> 16);
+              tot[j][4 * k + 1] += (ex >> 16) + (oy & 0xffffu);
+              tot[j][4 * k + 2] += (ey & 0xffffu) + (oy >> 16);
+              tot[j][4 * k + 3] += (ey >> 16) + (oxn & 0xffffu);
+              acc0[j][2 * k] = acc0[j][2 * k + 1] = 0u;
+              acc1[j][2 * k] = acc1[j][2 * k + 1] = 0u;
+            }
+        }
+      } else {
+        if (((c + 1) % kChanBlock) == 0 || c + 1 == nchans) {
+#pragma unroll
+          for (int j = 0; j < DW; ++j)
+#pragma unroll
+            for (int k = 0; k < NA; ++k) {
+              tot[j][k] += acc0[j][k];
+              acc0[j][k] = 0.f;
+            }
+        }
       }
     }
   }
 
+  if (lane == 63) return;  // the halo lane owns no output
   const int64_t nsamp = a.nsamp;
 #pragma unroll
   for (int j = 0; j < DW; ++j) {
     const int d = dw0 + j;
     if (d >= a.ndm) break;
+    if constexpr (kU8) {
 #pragma unroll
-    for (int k = 0; k < KS; ++k) {
-      const int64_t t = t0 + tw + 2 * lane + 128 * k;
-      if constexpr (sizeof(In) == 1) {
+      for (int k = 0; k < NR; ++k) {
+        const int64_t t = t0 + tw + 4 * lane + 252 * k;
         int32_t* o = static_cast<int32_t*>(a.out) + d * nsamp + t;
-        if (t + 1 < nsamp) {
-          const int2 w2 = make_int2(static_cast<int32_t>(tot[j][2 * k]), static_cast<int32_t>(tot[j][2 * k + 1]));
-          __builtin_memcpy(o, &w2, 8);
-        } else if (t < nsamp) {
-          *o = static_cast<int32_t>(tot[j][2 * k]);
+        if (t + 3 < nsamp) {
+          const int4 w4 = make_int4(static_cast<int32_t>(tot[j][4 * k]), static_cast<int32_t>(tot[j][4 * k + 1]),
+                                    static_cast<int32_t>(tot[j][4 * k + 2]), static_cast<int32_t>(tot[j][4 * k + 3]));
+          __builtin_memcpy(o, &w4, 16);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (t + i < nsamp) o[i] = static_cast<int32_t>(tot[j][4 * k + i]);
         }
-      } else {
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        const int64_t t = t0 + tw + 2 * lane + 126 * k;
         float* o = static_cast<float*>(a.out) + d * nsamp + t;
         if (t + 1 < nsamp) {
           const float2 w2 = make_float2(tot[j][2 * k], tot[j][2 * k + 1]);
@@ -475,29 +663,31 @@ struct Variant {
   }
 
 const Variant kVariants[] = {
-    DEDISP_VARIANT(2, 8, 8, 2, 2, 2),   // 16 trials x 2048 samples, 1024 threads
-    DEDISP_VARIANT(2, 8, 16, 1, 2, 2),  // 32 x 1024, 1024 threads
-    DEDISP_VARIANT(2, 8, 4, 4, 2, 2),   // 8 x 4096, 1024 threads
-    DEDISP_VARIANT(4, 8, 4, 2, 4, 2),   // 16 x 2048, 512 threads
-    DEDISP_VARIANT(2, 4, 8, 2, 2, 4),   // 16 x 1024, 1024 threads
-    DEDISP_VARIANT(4, 8, 2, 4, 4, 2),   // 8 x 4096, 512 threads
+    DEDISP_VARIANT(4, 8, 4, 2, 4, 2),   // 16 trials x 2016 samples, 512 threads
+    DEDISP_VARIANT(4, 8, 8, 1, 8, 2),   // 32 x 1008, 512 threads
+    DEDISP_VARIANT(4, 8, 2, 4, 4, 2),   // 8 x 4032, 512 threads
+    DEDISP_VARIANT(8, 4, 2, 4, 4, 2),   // 16 x 2016, 512 threads
+    DEDISP_VARIANT(4, 4, 8, 2, 2, 2),   // 32 x 2016, 1024 threads
+    DEDISP_VARIANT(2, 8, 8, 2, 2, 2),   // 16 x 2016, 1024 threads
 };
 constexpr int kNumTiled = sizeof(kVariants) / sizeof(kVariants[0]);
 
 constexpr size_t kMaxLds = 160 * 1024;
 
-// Floats per LDS copy a tiled variant needs for this plan (two copies x two
+// 4-sample units per LDS buffer a tiled variant needs for this plan (two
 // buffers live), or 0 if the plan's delay spread is too wide for the
-// variant's LDS or staging registers.
-int lds_pairs(dedisp_plan p, const Variant& v) {
+// variant's LDS or staging registers.  A window covers the tile's samples,
+// the delay spread of its trials, up to 3 samples of alignment in front and
+// the neighbour words read past the last sample.
+int lds_units(dedisp_plan p, const Variant& v) {
   const std::vector<int2>& w = host_windows(p, v.shape.dms());
   int spread = 0;
   for (const int2& x : w) spread = std::max(spread, x.y - x.x);
-  const int64_t n4 = (3 + static_cast<int64_t>(v.shape.samples()) + spread + 3) / 4;
+  const int64_t n4 = (3 + static_cast<int64_t>(spread) + v.shape.samples() + 7) / 4;
   if (n4 > static_cast<int64_t>(v.r) * v.shape.threads()) return 0;
-  const int64_t cap = 4 * n4;
-  if (4 * cap * 4 > static_cast<int64_t>(kMaxLds) - 256) return 0;  // 256 B for static LDS
-  return static_cast<int>(cap);
+  const int64_t unit = p->dtype == DEDISP_U8 ? 8 : 16;
+  if (2 * n4 * unit > static_cast<int64_t>(kMaxLds) - 256) return 0;  // 256 B for static LDS
+  return static_cast<int>(n4);
 }
 
 }  // namespace
@@ -509,7 +699,7 @@ TileShape variant_shape(int v) { return kVariants[v - 1].shape; }
 bool variant_fits(dedisp_plan p, int v) {
   if (v == 0) return true;
   if (v < 0 || v > kNumTiled) return false;
-  return lds_pairs(p, kVariants[v - 1]) > 0;
+  return lds_units(p, kVariants[v - 1]) > 0;
 }
 
 int default_variant(dedisp_plan p) {
@@ -576,8 +766,8 @@ int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, T
   int st = device_tables(p, dev, &dt);
   if (st != DEDISP_OK) return st;
   const Variant& var = kVariants[v - 1];
-  const int zcap = lds_pairs(p, var);
-  if (zcap == 0) return DEDISP_ERR_INVALID_ARG;
+  const int zunits = lds_units(p, var);
+  if (zunits == 0) return DEDISP_ERR_INVALID_ARG;
   const int2* win = nullptr;
   st = device_windows(p, dev, var.shape.dms(), &win);
   if (st != DEDISP_OK) return st;
@@ -595,7 +785,7 @@ int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, T
   a.ndm = p->ndm;
   a.ndm_pad = p->ndm_pad;
   a.nchans = p->nchans;
-  a.zcap = zcap;
+  a.zunits = zunits;
   a.n_dm_tiles = (p->ndm + var.shape.dms() - 1) / var.shape.dms();
   const int64_t n_t_tiles = (nsamp + var.shape.samples() - 1) / var.shape.samples();
   if (n_t_tiles > INT32_MAX / 64) return DEDISP_ERR_INVALID_ARG;
@@ -608,7 +798,7 @@ int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, T
   // a multiple of 8 groups, so that every XCD's run of blocks is whole groups
   const int64_t nblocks = (n_groups + 7) / 8 * 8 * a.gd * a.gt;
   if (nblocks > INT32_MAX) return DEDISP_ERR_INVALID_ARG;
-  *lds_out = 4 * static_cast<size_t>(zcap) * 4;
+  *lds_out = 2 * static_cast<size_t>(zunits) * (p->dtype == DEDISP_U8 ? 8 : 16);
   *nblocks_out = nblocks;
   *threads_out = var.shape.threads();
   return DEDISP_OK;
