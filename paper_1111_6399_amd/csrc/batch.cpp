@@ -193,7 +193,7 @@ int build_graph(dedisp_batch b, const void* const* ins, void* const* outs) {
   }
   // what solo launches need must exist before capture (allocations, attributes)
   for (size_t k = 0; k < b->solo.size(); ++k) {
-    const int st = dedisp::prepare(b->plans[b->solo[k]], b->solo_variant[k]);
+    const int st = dedisp::prepare(b->plans[b->solo[k]], b->solo_variant[k], b->nsamps[b->solo[k]]);
     if (st != DEDISP_OK) return st;
   }
   if ((e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed)) != hipSuccess)

@@ -17,6 +17,9 @@ namespace dedisp {
 
 // Float sums are accumulated in blocks of this many channels (see dedisp.h).
 constexpr int kChanBlock = 32;
+// Zero entries after the window-geometry table (covers the channels a kernel
+// reads ahead past the last one).
+constexpr int kGeoPad = 64;
 
 
 inline size_t dtype_size(int dtype) { return dtype == DEDISP_U8 ? 1 : dtype == DEDISP_F16 ? 2 : 4; }
@@ -39,6 +42,7 @@ struct TileShape {
 struct DeviceTables {
   int32_t* shift = nullptr;  // [nchans][ndm_pad]
   std::map<int, int2*> windows;  // dms-per-tile -> [ntiles][nchans]
+  std::map<int64_t, int2*> geo;  // (dms-per-tile, samples per tile, pitch mod 4) -> [ntiles][nchans]
 };
 
 // Arguments of one tiled launch (one beam); also the per-beam entry of the
@@ -51,12 +55,14 @@ struct TiledArgs {
   int64_t nsamp;
   const int32_t* shift;  // [nchans][ndm_pad]
   const int32_t* win;    // [n_dm_tiles][nchans][2] (min, max) delay
+  const int32_t* geo;    // [n_dm_tiles][nchans][2] (e, n4): window start and length (see device_geo)
   int ndm, ndm_pad, nchans;
-  int zunits;  // 4-sample units per LDS buffer
+  int zunits;  // 4-sample units per LDS slot (one channel of a stage)
   int n_dm_tiles, n_t_tiles;
   int gd, gt;       // tiles per group along trials and time
   int n_dm_groups;  // groups along trials
   int ntail;        // samples past total4 (0..3)
+  int max_shift;    // largest delay of the plan
 };
 
 struct BatchArgs {
@@ -92,6 +98,12 @@ int device_tables(dedisp_plan p, int device, DeviceTables** out);
 // Window table for a trial-tile size on the current device.
 int device_windows(dedisp_plan p, int device, int dms_per_tile, const int2** out);
 const std::vector<int2>& host_windows(dedisp_plan p, int dms_per_tile);
+// Window geometry of every (trial tile, channel) for tiles of `samples`
+// samples (a multiple of 4) and rows whose length is `pitch_mod4` modulo 4:
+// e = (window start alignment) - (minimum delay), so that the window of a tile
+// starting at sample t0 begins at absolute sample c*pitch + t0 - e (a multiple
+// of 4), and n4 = 4-sample units the window spans.
+int device_geo(dedisp_plan p, int device, int dms_per_tile, int samples, int pitch_mod4, const int2** out);
 
 // Kernel registry (kernels.hip).
 int variant_count();
@@ -110,7 +122,7 @@ int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, T
                int64_t* nblocks, int* threads);
 // Everything a launch of variant v of plan p needs that must not happen inside
 // a graph capture (device tables, kernel attributes), on the current device.
-int prepare(dedisp_plan p, int v);
+int prepare(dedisp_plan p, int v, int64_t nsamp);
 // Allow a kernel more than 64 KiB of dynamic LDS (once per kernel and device).
 int allow_large_lds(const void* fn);
 // Persistent batch kernel of variant v >= 1, and the counter reset kernel.

@@ -328,45 +328,287 @@ __device__ __forceinline__ uint32_t from_next_lane(uint32_t x) {
   return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(x), 0x134, 0xF, 0xF, false));
 }
 
-struct Geo {
+// Wait until at most N of this wave's vector memory operations are outstanding.
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  asm volatile("s_waitcnt vmcnt(%0)" ::"i"(N) : "memory");
+}
+
+// Buffer descriptor words for `bytes` bytes from `p` (raw buffer, range
+// checked: reads past the end return zero without touching memory).
+__device__ __forceinline__ v4i buffer_words(const void* p, int64_t bytes) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  v4i w;
+  w.x = static_cast<int>(a & 0xffffffffu);
+  w.y = static_cast<int>((a >> 32) & 0xffffu);
+  w.z = static_cast<int>(bytes);
+  w.w = 0x00020000;
+  return w;
+}
+
+// 16 bytes per lane from byte offset voff of the buffer straight into LDS at
+// lds + 16*lane, for the lanes whose unit index u is below n (the others do
+// nothing; the load still counts once in this wave's vector memory counter).
+__device__ __forceinline__ void lds_dma16(uint32_t lds, uint32_t voff, const v4i& rs, int n, uint32_t u) {
+  uint64_t save;
+  asm volatile(
+      "v_cmp_gt_i32 vcc, %[n], %[u]\n\t"
+      "s_and_saveexec_b64 %[sv], vcc\n\t"
+      "s_mov_b32 m0, %[lds]\n\t"
+      "s_nop 0\n\t"
+      "buffer_load_dwordx4 %[vo], %[rs], 0 offen lds\n\t"
+      "s_mov_b64 exec, %[sv]"
+      : [sv] "=&s"(save)
+      : [n] "s"(n), [u] "v"(u), [lds] "s"(lds), [vo] "v"(voff), [rs] "s"(rs)
+      : "vcc", "memory");
+}
+
+// Workgroup barrier after this wave's LDS writes have completed.  Writes that
+// go to LDS through the vector memory path are waited for explicitly before.
+__device__ __forceinline__ void lds_barrier_asm() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Float input, staged by loads that write LDS directly (no registers): a ring
+// of NS = 2*CG channel slots, the windows of the next NS-1 channels in flight
+// while a channel is accumulated.  A slot holds R*NT units; wave w loads units
+// [r*NT + 64w, r*NT + 64w + 64) of a window with its r-th load (16 bytes per
+// lane).  Lanes past the window are masked off except lane 0, so that every
+// wave issues exactly R loads per channel and waits for its loads of the
+// channel about to be used with a constant count; a barrier then makes every
+// wave's loads visible.  One buffer descriptor covers the whole input (32-bit
+// byte offsets).  Window start and length come from a table built on the host
+// per (trial tile, channel); the scalar loads of the table and of the delays
+// run a channel ahead, and both tables are padded so that reading past the
+// last channel needs no check.
+template <int DW, int KS, int WD, int WT, int R, int CG>
+__device__ __forceinline__ void tile_f32_dma(const TiledArgs& a, int dm_tile, int t_tile) {
+  constexpr int NT = 64 * WD * WT;
+  constexpr int SPW = 126 * KS;
+  constexpr int T = SPW * WT;
+  constexpr int NR = KS;
+  constexpr int NS = 2 * CG;
+  constexpr int D = 2;
+  static_assert(KS % 2 == 0 && (D - 1) * NR <= 15, "tile shape");
+  static_assert(NS >= 2 && kChanBlock % NS == 0, "ring size");
+  static_assert((NS - 2) * R <= 63, "vector memory counter");
+  extern __shared__ float4 lds4[];
+  const float* __restrict__ in = static_cast<const float*>(a.in);
+  typedef __attribute__((address_space(3))) char lds_char;
+  lds_char* l3 = (lds_char*)(__attribute__((address_space(3))) void*)lds4;
+
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  const int wd = wave % WD;
+  const int wt = wave / WD;
+  const int t0 = t_tile * T;  // the input is below 2^32 bytes, so are these indices
+  const int dw0 = dm_tile * (DW * WD) + wd * DW;
+  const int tw = wt * SPW;
+  const int nchans = a.nchans;
+  const int pitch = static_cast<int>(a.pitch);
+  const uint32_t slot_bytes = static_cast<uint32_t>(a.zunits) * 16u;
+  const uint32_t vlane = lds_addr(lds4) + 8u * static_cast<uint32_t>(lane);
+
+  float tail[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (k < a.ntail) tail[k] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(in[a.total4 + k])));
+  // First channel whose window can reach the partial last group of the input
+  // (a window ends before c*pitch + t0 + max_shift + T + 10).
+  int c_tail;
+  {
+    const int64_t lim = a.total4 - t0 - a.max_shift - (T + 10);
+    c_tail = lim < 0 ? 0 : static_cast<int>(lim / a.pitch) + 1;
+  }
+
+  // Loads of the window (start e, length n4 units) whose channel row starts at
+  // byte 4*(row + t0) = cbase, into slot s.  A load whose lanes are all past
+  // the window still issues (with no lane active it counts as done without
+  // touching memory or LDS), so the count per channel is always R.
+  uint32_t cbase = 4u * static_cast<uint32_t>(t0);
+  uint32_t ur[R], uoff[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    ur[r] = static_cast<uint32_t>(tid + r * NT);
+    uoff[r] = 16u * ur[r];
+  }
+  const v4i rs = buffer_words(in, a.total4 * 4);
+  const uint32_t ldsw = lds_addr(lds4) + 16u * static_cast<uint32_t>(64 * wave);
+  auto load = [&](int s, int e, int n4) {
+    const uint32_t base = cbase - 4u * static_cast<uint32_t>(e);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      lds_dma16(ldsw + s * slot_bytes + 16u * (r * NT), base + uoff[r], rs, n4, ur[r]);
+    cbase += 4u * static_cast<uint32_t>(pitch);
+  };
+
+  float part[DW][2 * NR];
+  float tot[DW][2 * NR];
+#pragma unroll
+  for (int j = 0; j < DW; ++j)
+#pragma unroll
+    for (int k = 0; k < 2 * NR; ++k) part[j][k] = tot[j][k] = 0.f;
+
+  cint32* gp = (cint32*)(a.geo) + 2 * static_cast<int64_t>(dm_tile) * nchans;  // next (e, n4) to read
+  int eq[NS], nq[NS];  // window of the channel in each slot
+#pragma unroll
+  for (int u = 0; u < NS - 1; ++u) {
+    eq[u] = gp[0];
+    nq[u] = gp[1];
+    gp += 2;
+    load(u, eq[u], nq[u]);
+  }
+  int en = gp[0], nn = gp[1];  // window of the next channel to load
+  gp += 2;
+  cint32* sp = (cint32*)(a.shift) + dw0;  // delays of the channel about to be accumulated
+  int sh[DW];
+#pragma unroll
+  for (int j = 0; j < DW; ++j) sh[j] = sp[j];
+  sp += a.ndm_pad;
+
+  for (int cb = 0; cb < nchans; cb += NS) {
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int c = cb + u;
+      if (c >= nchans) break;
+      wait_vm<(NS - 2) * R>();  // this wave's loads of channel c are in LDS
+      if (c >= c_tail) {
+        const int64_t a0 = static_cast<int64_t>(c) * pitch + t0 - eq[u];
+        if (a0 + 4 * static_cast<int64_t>(nq[u]) > a.total4) {  // the window holds the partial last group
+          const int itail = static_cast<int>(a.total4 - a0) >> 2;
+          if (tid == itail % NT && itail / NT < R)
+            *reinterpret_cast<float4*>(reinterpret_cast<char*>(lds4) + u * slot_bytes +
+                                       16 * ((itail / NT) * NT + 64 * (itail % NT / 64)) + 16 * (itail % 64)) =
+                make_float4(tail[0], tail[1], tail[2], 0.f);
+        }
+      }
+      lds_barrier_asm();
+      const int eo = eq[u] + tw;
+      uint32_t ba[DW];
+      int pb[DW];
+#pragma unroll
+      for (int j = 0; j < DW; ++j) {
+        pb[j] = sh[j] + eo;
+        ba[j] = vlane + (u * slot_bytes + 4u * static_cast<uint32_t>(pb[j] & ~1));
+      }
+      v2u rb[D][NR];
+      lds_reads<NR>(ba[0], rb[0]);
+      // the slot of channel c-1 is free: load channel c+NS-1 into it, then
+      // start the scalar loads of the next channel (used one channel later)
+      {
+        const int un = (u + NS - 1) % NS;
+        eq[un] = en;
+        nq[un] = nn;
+        load(un, en, nn);
+        en = gp[0];
+        nn = gp[1];
+        gp += 2;
+      }
+      int shn[DW];
+#pragma unroll
+      for (int j = 0; j < DW; ++j) shn[j] = sp[j];
+      sp += a.ndm_pad;
+#pragma unroll
+      for (int j = 0; j < DW; ++j) {
+        if (j + 1 < DW) {
+          lds_reads<NR>(ba[j + 1], rb[(j + 1) % D]);
+          lds_wait<NR>();
+        } else {
+          lds_wait<0>();
+        }
+        TrialAdds<NR>::f32(part[j], rb[j % D], pb[j]);
+      }
+      if (u == NS - 1 && ((cb + NS) % kChanBlock) == 0) {
+#pragma unroll
+        for (int j = 0; j < DW; ++j)
+#pragma unroll
+          for (int k = 0; k < 2 * NR; ++k) {
+            tot[j][k] += part[j][k];
+            part[j][k] = 0.f;
+          }
+      }
+#pragma unroll
+      for (int j = 0; j < DW; ++j) sh[j] = shn[j];
+    }
+  }
+  // the channels after the last whole block of kChanBlock
+#pragma unroll
+  for (int j = 0; j < DW; ++j)
+#pragma unroll
+    for (int k = 0; k < 2 * NR; ++k) tot[j][k] += part[j][k];
+  wait_vm<0>();  // no load may still be writing LDS when the workgroup ends
+
+  if (lane == 63) return;  // the halo lane owns no output
+  const int64_t nsamp = a.nsamp;
+#pragma unroll
+  for (int j = 0; j < DW; ++j) {
+    const int d = dw0 + j;
+    if (d >= a.ndm) break;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const int64_t t = static_cast<int64_t>(t0) + tw + 2 * lane + 126 * k;
+      float* o = static_cast<float*>(a.out) + d * nsamp + t;
+      if (t + 1 < nsamp) {
+        const float2 w2 = make_float2(tot[j][2 * k], tot[j][2 * k + 1]);
+        __builtin_memcpy(o, &w2, 8);
+      } else if (t < nsamp) {
+        *o = tot[j][2 * k];
+      }
+    }
+  }
+}
+
+// Scalar geometry of one channel's window in a stage.
+struct Win {
   int64_t a0;  // first staged sample (absolute index, a multiple of 4)
-  int off;     // window index of the wave's first output sample at delay 0
+  int64_t rem; // samples from a0 to the end of the whole groups of 4 of the input
   int n4;      // 4-sample units staged
+  int off;     // window index of the wave's first output sample at delay 0
 };
 
 // Workgroup tile: WD*DW trials x WT*126*KS samples.  Wave (wd, wt) owns DW
 // trials and 126*KS consecutive samples of each.
 //
-// Per channel the workgroup stages the window of input its tile needs into
-// LDS once.  Float and half input is staged as float32 (16 bytes per 4
-// samples); 8-bit input as pairs of samples in the two 16-bit halves of a
-// word (8 bytes per 4 samples), so that one 32-bit add accumulates two
-// samples exactly (a half holds 256 channels of 255 before it could carry).
+// Channels are processed in stages of CG.  For a stage the workgroup stages,
+// per channel, the window of input the tile needs into LDS (one slot per
+// channel, two stages alternate), with one barrier per stage; the global
+// loads of the next stage are in flight in registers meanwhile (R 4-sample
+// units per thread and channel).  Float and half input is staged as float32
+// (16 bytes per 4 samples); 8-bit input as pairs of samples in the two 16-bit
+// halves of a word (8 bytes per 4 samples), so that one 32-bit add
+// accumulates two samples exactly (a half holds 256 channels of 255 before
+// it could carry).
 //
-// A trial reads its samples with aligned 64-bit reads.  Lanes 0-62 own the
-// output samples; lane 63 only supplies its neighbour when the trial's window
-// position is not a multiple of the word pair (float: odd sample; 8-bit: odd
-// word).  8-bit input has a second alignment, the sample within a word: odd
-// positions accumulate into a second set of words that holds every sum one
-// sample earlier, and the two sets are combined into 32-bit totals every 256
-// channels.  The delay and the alignment only enter a wave-uniform address
-// and a uniform branch.
+// A (channel, trial) block reads its samples with aligned 64-bit reads.
+// Lanes 0-62 own the output samples; lane 63 only supplies its neighbour when
+// the block's window position is not a multiple of the word pair (float: odd
+// sample; 8-bit: odd word).  8-bit input has a second alignment, the sample
+// within a word: odd positions accumulate into a second set of words that
+// holds every sum one sample earlier, and the two sets are combined into
+// 32-bit totals every 256 channels.  The delay and the alignment only enter
+// a wave-uniform address and a uniform branch.  The reads of the next blocks
+// of the stage are in flight while a block is added.
 //
 // Float sums: channels ascending, summed in blocks of kChanBlock into a
 // partial that is then added to the total (the same order in every variant).
-//
-// Two LDS buffers alternate with one barrier per channel; the global loads run
-// P channels ahead in P register sets of R 4-sample units per thread.
-template <typename In, int DW, int KS, int WD, int WT, int R, int P>
+template <typename In, int DW, int KS, int WD, int WT, int R, int CG>
 __device__ __forceinline__ void tile_body(const TiledArgs& a, int dm_tile, int t_tile) {
+  if constexpr (std::is_same<In, float>::value) {
+    tile_f32_dma<DW, KS, WD, WT, R, CG>(a, dm_tile, t_tile);
+    return;
+  }
   constexpr bool kU8 = sizeof(In) == 1;
   constexpr int NT = 64 * WD * WT;
   constexpr int SPW = 126 * KS;          // output samples per wave and trial
   constexpr int T = SPW * WT;            // output samples per tile
-  constexpr int NR = kU8 ? KS / 2 : KS;  // 64-bit reads per lane and trial
+  constexpr int NR = kU8 ? KS / 2 : KS;  // 64-bit reads per lane and block
   constexpr int UB = kU8 ? 8 : 16;       // LDS bytes per 4-sample unit
+  constexpr int NB = CG * DW;            // (channel, trial) blocks per stage
+  constexpr int D = (3 - 1) * NR <= 15 ? 3 : 2;  // blocks with reads in flight
   static_assert(KS % 2 == 0, "KS must be even");
-  static_assert(NR <= 15, "the LDS wait counter holds at most 15");
+  static_assert((D - 1) * NR <= 15, "the LDS wait counter holds at most 15");
+  static_assert((kU8 ? 256 : kChanBlock) % CG == 0, "a stage must not straddle a flush");
   extern __shared__ float4 lds4[];
   const In* __restrict__ in = static_cast<const In*>(a.in);
 
@@ -381,8 +623,10 @@ __device__ __forceinline__ void tile_body(const TiledArgs& a, int dm_tile, int t
   cint32* wrow = (cint32*)(a.win) + 2 * static_cast<int64_t>(dm_tile) * a.nchans;
   cint32* srow = (cint32*)(a.shift) + dw0;
   const int nchans = a.nchans;
-  const uint32_t buf_bytes = static_cast<uint32_t>(a.zunits) * UB;
+  const int nlast = nchans - 1;
+  const uint32_t slot_bytes = static_cast<uint32_t>(a.zunits) * UB;
   const uint32_t lds0 = lds_addr(lds4);
+  const uint32_t vlane = lds0 + 8u * static_cast<uint32_t>(lane);
 
   // The last 1-3 samples of the input (past the last whole group of 4) are
   // read once here; a window that reaches them patches them in.
@@ -397,27 +641,28 @@ __device__ __forceinline__ void tile_body(const TiledArgs& a, int dm_tile, int t
             __builtin_amdgcn_readfirstlane(__float_as_int(Elem<In>::get(in, a.total4 + k))));
     }
 
-  // Window of channel c; `row` = c*pitch + t0.
-  auto geo = [&](int c, int64_t row) {
-    const int lo = wrow[2 * c];
-    const int hi = wrow[2 * c + 1];
-    Geo g;
-    const int64_t w0 = row + lo;
+  // Window of channel c (clamped to the last channel past the end).
+  auto window = [&](int c) {
+    const int cc = min(c, nlast);
+    const int lo = wrow[2 * cc];
+    const int hi = wrow[2 * cc + 1];
+    Win g;
+    const int64_t w0 = static_cast<int64_t>(cc) * a.pitch + t0 + lo;
     g.a0 = w0 & ~static_cast<int64_t>(3);
     const int mis = static_cast<int>(w0) & 3;
     g.n4 = (mis + (hi - lo) + (T + 7)) >> 2;
     g.off = mis + tw - lo;
+    g.rem = a.total4 - g.a0;
     return g;
   };
 
-  // Global loads of one channel's window into a register set.  `live` false
-  // issues the same instructions against an empty range (they return zeros
-  // without touching memory), so that every iteration issues the same number
-  // of loads and the waits stay exact.
-  auto issue = [&](const Geo& g, Raw<In>* rs, bool live) {
-    const int64_t have = a.total4 - g.a0;
+  // Global loads of one channel's window.  Past the last channel the same
+  // instructions run against an empty range (they return zeros without
+  // touching memory), so every stage issues the same number of loads and the
+  // compiler's waits stay exact.
+  auto issue = [&](const Win& g, Raw<In>* rs, bool live) {
     const int want = 4 * g.n4;
-    const int n = have < want ? static_cast<int>(have) : want;
+    const int n = g.rem < want ? static_cast<int>(g.rem) : want;
     const int num = live ? n * static_cast<int>(sizeof(In)) : 0;
     const __amdgpu_buffer_rsrc_t rsrc =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<In*>(in + g.a0), 0, num, 0x00020000);
@@ -439,119 +684,128 @@ __device__ __forceinline__ void tile_body(const TiledArgs& a, int dm_tile, int t
     }
   };
 
-  // Accumulators.  Float: part (current block of channels) and tot.  8-bit:
-  // ev/od words of two 16-bit sums (od one sample earlier), and 32-bit tot.
-  constexpr int NA = 2 * NR;  // accumulator words per trial and set
+  // Accumulators.  Float: acc0 = partial of the current block of channels,
+  // tot = total.  8-bit: acc0/acc1 = words of two 16-bit sums (acc1 one
+  // sample earlier), tot = 32-bit totals.
+  constexpr int NA = 2 * NR;
   typedef typename std::conditional<kU8, uint32_t, float>::type Acc;
-  Acc acc0[DW][NA];  // float: part; 8-bit: ev
-  Acc acc1[DW][NA];  // float: unused; 8-bit: od
+  Acc acc0[DW][NA];
+  Acc acc1[DW][kU8 ? NA : 1];
   Acc tot[DW][kU8 ? 4 * NR : NA];
 #pragma unroll
   for (int j = 0; j < DW; ++j) {
 #pragma unroll
-    for (int k = 0; k < NA; ++k) {
-      acc0[j][k] = 0;
-      acc1[j][k] = 0;
-    }
+    for (int k = 0; k < NA; ++k) acc0[j][k] = 0;
+#pragma unroll
+    for (int k = 0; k < (kU8 ? NA : 1); ++k) acc1[j][k] = 0;
 #pragma unroll
     for (int k = 0; k < (kU8 ? 4 * NR : NA); ++k) tot[j][k] = 0;
   }
 
-  Raw<In> raw[P][R];
-  Geo gq[P];
-  int64_t row = t0;  // c*pitch + t0 of the next channel to load
+  Raw<In> raw[CG][R];
+  Win gq[CG];
 #pragma unroll
-  for (int u = 0; u < P; ++u) {
-    gq[u] = geo(min(u, nchans - 1), row);
+  for (int u = 0; u < CG; ++u) {
+    gq[u] = window(u);
     issue(gq[u], raw[u], u < nchans);
-    row += a.pitch;
   }
 
-  for (int cb = 0; cb < nchans; cb += P) {
+  const int nstages = (nchans + CG - 1) / CG;
+  for (int s = 0; s < nstages; ++s) {
+    const int c0 = s * CG;
+    const uint32_t sbase = (s & 1) ? CG * slot_bytes : 0u;
+    int off[CG];
+    int sh[CG][DW];
 #pragma unroll
-    for (int u = 0; u < P; ++u) {
-      const int c = cb + u;
-      const uint32_t boff = (c & 1) ? buf_bytes : 0u;
-      const Geo g = gq[u];
-      // Delays of this wave's trials at channel c, read before the barrier:
-      // the barrier's wait then covers these scalar loads too.
-      int sh[DW];
-      {
-        cint32* sr = srow + static_cast<int64_t>(min(c, nchans - 1)) * a.ndm_pad;
+    for (int u = 0; u < CG; ++u) {
+      const Win g = gq[u];
+      const uint32_t boff = sbase + u * slot_bytes;
+      off[u] = g.off;
+      // Delays of this wave's trials at the channel, read before the barrier
+      // so that its wait covers these scalar loads too.
+      cint32* sr = srow + static_cast<int64_t>(min(c0 + u, nlast)) * a.ndm_pad;
 #pragma unroll
-        for (int j = 0; j < DW; ++j) sh[j] = sr[j];
-      }
-      // Hand the window of channel c to LDS.  Past the last channel this
-      // writes zeros nobody reads.
-      if (__builtin_expect(g.a0 + 4 * static_cast<int64_t>(g.n4) <= a.total4, 1)) {
+      for (int j = 0; j < DW; ++j) sh[u][j] = sr[j];
+      // Hand the window to LDS: a wave writes a run of 64 units when the run
+      // starts inside the window (the slot has 64 units of slack after it).
+      // (a stage's channels past the last one stay all zeros)
+      if (__builtin_expect(g.rem >= 4 * static_cast<int64_t>(g.n4) || c0 + u > nlast, 1)) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int i = tid + r * NT;
-          if (i < g.n4) put(boff, i, raw[u][r], false);
-        }
+        for (int r = 0; r < R; ++r)
+          if (r * NT + 64 * wave < g.n4) put(boff, tid + r * NT, raw[u][r], false);
       } else {  // the window reaches the last, partial group of the input
-        const int itail = static_cast<int>((a.total4 - g.a0) >> 2);  // unit holding the tail
+        const int itail = static_cast<int>(g.rem >> 2);  // unit holding the tail
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int i = tid + r * NT;
-          if (i < g.n4) put(boff, i, raw[u][r], i == itail);
-        }
+        for (int r = 0; r < R; ++r)
+          if (r * NT + 64 * wave < g.n4) put(boff, tid + r * NT, raw[u][r], tid + r * NT == itail);
       }
-      gq[u] = geo(min(c + P, nchans - 1), row);
-      issue(gq[u], raw[u], c + P < nchans);
-      row += a.pitch;
-      lds_barrier();
-      if (c >= nchans) continue;
+    }
+#pragma unroll
+    for (int u = 0; u < CG; ++u) {
+      gq[u] = window(c0 + CG + u);
+      issue(gq[u], raw[u], c0 + CG + u < nchans);
+    }
+    lds_barrier();
 
-      const uint32_t vb = lds0 + boff + 8u * static_cast<uint32_t>(lane);
-      int pj[DW];
+    // (channel, trial) blocks of the stage, reads D blocks ahead.  Channels
+    // past the last one read zeros and add nothing.
+    uint32_t ba[NB];
+    int pb[NB];
 #pragma unroll
-      for (int j = 0; j < DW; ++j) pj[j] = sh[j] + g.off;  // window index of the wave's first sample
-      auto addr = [&](int p) -> uint32_t {
-        return kU8 ? vb + 8u * static_cast<uint32_t>(p >> 2) : vb + 4u * static_cast<uint32_t>(p & ~1);
-      };
-      v2u rb[2][NR];
-      lds_reads<NR>(addr(pj[0]), rb[0]);
+    for (int b = 0; b < NB; ++b) {
+      const int u = b / DW, j = b % DW;
+      const int p = sh[u][j] + off[u];
+      pb[b] = p;
+      ba[b] = vlane + sbase + u * slot_bytes +
+              (kU8 ? 8u * static_cast<uint32_t>(p >> 2) : 4u * static_cast<uint32_t>(p & ~1));
+    }
+    v2u rb[D][NR];
 #pragma unroll
-      for (int j = 0; j < DW; ++j) {
-        if (j + 1 < DW) {
-          lds_reads<NR>(addr(pj[j + 1]), rb[(j + 1) & 1]);
-          lds_wait<NR>();
-        } else {
-          lds_wait<0>();
-        }
-        if constexpr (kU8)
-          TrialAdds<NR>::u8(acc0[j], acc1[j], rb[j & 1], pj[j]);
-        else
-          TrialAdds<NR>::f32(acc0[j], rb[j & 1], pj[j]);
+    for (int b = 0; b < D && b < NB; ++b) lds_reads<NR>(ba[b], rb[b]);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int ahead = (NB - 1 - b) < (D - 1) ? (NB - 1 - b) : (D - 1);
+      if (ahead >= 2)
+        lds_wait<2 * NR>();
+      else if (ahead == 1)
+        lds_wait<NR>();
+      else
+        lds_wait<0>();
+      const int j = b % DW;
+      if constexpr (kU8)
+        TrialAdds<NR>::u8(acc0[j], acc1[j], rb[b % D], pb[b]);
+      else
+        TrialAdds<NR>::f32(acc0[j], rb[b % D], pb[b]);
+      if (b + D < NB) lds_reads<NR>(ba[b + D], rb[(b + D) % D]);
+    }
+
+    const int c1 = c0 + CG;  // channels done after this stage
+    if constexpr (kU8) {
+      if ((c1 & 255) == 0 || c1 >= nchans) {
+#pragma unroll
+        for (int j = 0; j < DW; ++j)
+#pragma unroll
+          for (int k = 0; k < NR; ++k) {
+            const uint32_t ex = acc0[j][2 * k], ey = acc0[j][2 * k + 1];
+            const uint32_t ox = acc1[j][2 * k], oy = acc1[j][2 * k + 1];
+            const uint32_t oxn = from_next_lane(ox);
+            tot[j][4 * k + 0] += (ex & 0xffffu) + (ox >> 16);
+            tot[j][4 * k + 1] += (ex >> 16) + (oy & 0xffffu);
+            tot[j][4 * k + 2] += (ey & 0xffffu) + (oy >> 16);
+            tot[j][4 * k + 3] += (ey >> 16) + (oxn & 0xffffu);
+            acc0[j][2 * k] = acc0[j][2 * k + 1] = 0u;
+            acc1[j][2 * k] = acc1[j][2 * k + 1] = 0u;
+          }
       }
-      if constexpr (kU8) {
-        if (((c + 1) & 255) == 0 || c + 1 == nchans) {
+    } else {
+      if ((c1 % kChanBlock) == 0 || c1 >= nchans) {
 #pragma unroll
-          for (int j = 0; j < DW; ++j)
+        for (int j = 0; j < DW; ++j)
 #pragma unroll
-            for (int k = 0; k < NR; ++k) {
-              const uint32_t ex = acc0[j][2 * k], ey = acc0[j][2 * k + 1];
-              const uint32_t ox = acc1[j][2 * k], oy = acc1[j][2 * k + 1];
-              const uint32_t oxn = from_next_lane(ox);
-              tot[j][4 * k + 0] += (ex & 0xffffu) + (ox >> 16);
-              tot[j][4 * k + 1] += (ex >> 16) + (oy & 0xffffu);
-              tot[j][4 * k + 2] += (ey & 0xffffu) + (oy >> 16);
-              tot[j][4 * k + 3] += (ey >> 16) + (oxn & 0xffffu);
-              acc0[j][2 * k] = acc0[j][2 * k + 1] = 0u;
-              acc1[j][2 * k] = acc1[j][2 * k + 1] = 0u;
-            }
-        }
-      } else {
-        if (((c + 1) % kChanBlock) == 0 || c + 1 == nchans) {
-#pragma unroll
-          for (int j = 0; j < DW; ++j)
-#pragma unroll
-            for (int k = 0; k < NA; ++k) {
-              tot[j][k] += acc0[j][k];
-              acc0[j][k] = 0.f;
-            }
-        }
+          for (int k = 0; k < NA; ++k) {
+            tot[j][k] += acc0[j][k];
+            acc0[j][k] = 0.f;
+          }
       }
     }
   }
@@ -593,18 +847,18 @@ __device__ __forceinline__ void tile_body(const TiledArgs& a, int dm_tile, int t
   }
 }
 
-template <typename In, int DW, int KS, int WD, int WT, int R, int P>
+template <typename In, int DW, int KS, int WD, int WT, int R, int CG>
 __global__ __launch_bounds__(64 * WD * WT) void dedisp_tiled(const TiledArgs a) {
   int dm_tile, t_tile;
   if (!tile_of(a, dm_tile, t_tile)) return;  // padding block of the last group
-  tile_body<In, DW, KS, WD, WT, R, P>(a, dm_tile, t_tile);
+  tile_body<In, DW, KS, WD, WT, R, CG>(a, dm_tile, t_tile);
 }
 
 // Persistent batch kernel: resident workgroups pull (beam, trial tile, time
 // tile) items from one atomic counter until none are left.  Items are
 // numbered beam by beam, beams in order of decreasing cost per item (longest
 // items first), and inside a beam in the same groups as a single launch.
-template <int DW, int KS, int WD, int WT, int R, int P>
+template <int DW, int KS, int WD, int WT, int R, int CG>
 __global__ __launch_bounds__(64 * WD * WT) void dedisp_batch_persistent(const BatchArgs b) {
   __shared__ long long item_s;
   for (;;) {
@@ -631,11 +885,11 @@ __global__ __launch_bounds__(64 * WD * WT) void dedisp_batch_persistent(const Ba
     if (dm_tile < a.n_dm_tiles && t_tile < a.n_t_tiles) {
       const int dt = ((cint32*)(b.dtype))[beam];
       if (dt == DEDISP_F32)
-        tile_body<float, DW, KS, WD, WT, R, P>(a, dm_tile, t_tile);
+        tile_body<float, DW, KS, WD, WT, R, CG>(a, dm_tile, t_tile);
       else if (dt == DEDISP_U8)
-        tile_body<uint8_t, DW, KS, WD, WT, R, P>(a, dm_tile, t_tile);
+        tile_body<uint8_t, DW, KS, WD, WT, R, CG>(a, dm_tile, t_tile);
       else
-        tile_body<__half, DW, KS, WD, WT, R, P>(a, dm_tile, t_tile);
+        tile_body<__half, DW, KS, WD, WT, R, CG>(a, dm_tile, t_tile);
     }
     lds_barrier();  // every wave is done with this item's LDS before the next
   }
@@ -647,47 +901,60 @@ __global__ void reset_counter(unsigned long long* c) { *c = 0ull; }
 
 struct Variant {
   TileShape shape;
-  int r;              // staging 4-sample slots per thread
-  int p;              // channels of prefetch
+  int r;              // staging 4-sample units per thread and channel
+  int cg;             // channels per stage
   const void* fn[3];  // by dtype: U8, F16, F32
   const void* batch;  // persistent batch kernel
 };
 
-#define DEDISP_VARIANT(DW, KS, WD, WT, R, P)                                                        \
+#define DEDISP_VARIANT(DW, KS, WD, WT, R, CG)                                                       \
   Variant {                                                                                        \
-    TileShape{DW, KS, WD, WT}, R, P,                                                               \
-        {reinterpret_cast<const void*>(&dedisp_tiled<uint8_t, DW, KS, WD, WT, R, P>),               \
-         reinterpret_cast<const void*>(&dedisp_tiled<__half, DW, KS, WD, WT, R, P>),                \
-         reinterpret_cast<const void*>(&dedisp_tiled<float, DW, KS, WD, WT, R, P>)},                \
-        reinterpret_cast<const void*>(&dedisp_batch_persistent<DW, KS, WD, WT, R, P>)               \
+    TileShape{DW, KS, WD, WT}, R, CG,                                                              \
+        {reinterpret_cast<const void*>(&dedisp_tiled<uint8_t, DW, KS, WD, WT, R, CG>),              \
+         reinterpret_cast<const void*>(&dedisp_tiled<__half, DW, KS, WD, WT, R, CG>),               \
+         reinterpret_cast<const void*>(&dedisp_tiled<float, DW, KS, WD, WT, R, CG>)},               \
+        reinterpret_cast<const void*>(&dedisp_batch_persistent<DW, KS, WD, WT, R, CG>)              \
   }
 
 const Variant kVariants[] = {
-    DEDISP_VARIANT(4, 8, 4, 2, 4, 2),   // 16 trials x 2016 samples, 512 threads
-    DEDISP_VARIANT(4, 8, 8, 1, 8, 2),   // 32 x 1008, 512 threads
-    DEDISP_VARIANT(4, 8, 2, 4, 4, 2),   // 8 x 4032, 512 threads
-    DEDISP_VARIANT(8, 4, 2, 4, 4, 2),   // 16 x 2016, 512 threads
-    DEDISP_VARIANT(4, 4, 8, 2, 2, 2),   // 32 x 2016, 1024 threads
-    DEDISP_VARIANT(2, 8, 8, 2, 2, 2),   // 16 x 2016, 1024 threads
+    DEDISP_VARIANT(4, 8, 4, 2, 4, 2),  // 16 trials x 2016 samples, 512 threads, 2 channels per stage
+    DEDISP_VARIANT(4, 8, 4, 2, 4, 1),  // 16 x 2016, 512 threads, 1 channel per stage
+    DEDISP_VARIANT(4, 8, 2, 4, 4, 2),  // 8 x 4032, 512 threads
+    DEDISP_VARIANT(4, 8, 4, 2, 4, 4),  // 16 x 2016, 512 threads, 4 channels per stage
+    DEDISP_VARIANT(2, 8, 8, 2, 2, 2),  // 16 x 2016, 1024 threads
+    DEDISP_VARIANT(8, 4, 2, 4, 4, 2),  // 16 x 2016, 512 threads
+    DEDISP_VARIANT(4, 8, 8, 1, 8, 2),  // 32 x 1008, 512 threads
 };
 constexpr int kNumTiled = sizeof(kVariants) / sizeof(kVariants[0]);
 
 constexpr size_t kMaxLds = 160 * 1024;
 
-// 4-sample units per LDS buffer a tiled variant needs for this plan (two
-// buffers live), or 0 if the plan's delay spread is too wide for the
+// 4-sample units per LDS slot (one channel's window) a tiled variant needs
+// for this plan, or 0 if the plan's delay spread is too wide for the
 // variant's LDS or staging registers.  A window covers the tile's samples,
 // the delay spread of its trials, up to 3 samples of alignment in front and
-// the neighbour words read past the last sample.
+// the neighbour words read past the last sample; a slot has 64 units of
+// slack for the last wave-wide run of writes.  Two stages of `cg` slots are
+// live.
 int lds_units(dedisp_plan p, const Variant& v) {
   const std::vector<int2>& w = host_windows(p, v.shape.dms());
   int spread = 0;
   for (const int2& x : w) spread = std::max(spread, x.y - x.x);
   const int64_t n4 = (3 + static_cast<int64_t>(spread) + v.shape.samples() + 7) / 4;
   if (n4 > static_cast<int64_t>(v.r) * v.shape.threads()) return 0;
+  // float input: a slot holds one 64-unit run per wave and load (R*NT units)
+  const int64_t units = p->dtype == DEDISP_F32 ? static_cast<int64_t>(v.r) * v.shape.threads() : n4 + 64;
   const int64_t unit = p->dtype == DEDISP_U8 ? 8 : 16;
-  if (2 * n4 * unit > static_cast<int64_t>(kMaxLds) - 256) return 0;  // 256 B for static LDS
-  return static_cast<int>(n4);
+  if (2 * v.cg * units * unit > static_cast<int64_t>(kMaxLds) - 256) return 0;  // 256 B for static LDS
+  return static_cast<int>(units);
+}
+
+// The tiled float kernel addresses its input with 32-bit byte offsets,
+// including the rows it reads ahead past the last channel.
+bool f32_offsets_fit(dedisp_plan p, int64_t nsamp) {
+  const int64_t pitch = nsamp + p->max_shift;
+  return (static_cast<int64_t>(p->nchans) + 16) * pitch * 4 + (static_cast<int64_t>(1) << 24) <
+         (static_cast<int64_t>(1) << 32);
 }
 
 }  // namespace
@@ -703,7 +970,7 @@ bool variant_fits(dedisp_plan p, int v) {
 }
 
 int default_variant(dedisp_plan p) {
-  static const int order[] = {1, 2, 3, 4, 5, 6};
+  static const int order[] = {1, 2, 3, 4, 5, 6, 7};
   for (int v : order)
     if (v <= kNumTiled && variant_fits(p, v)) return v;
   return 0;
@@ -718,6 +985,9 @@ int launch(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, hipSt
   if (st != DEDISP_OK) return st;
   const int64_t pitch = nsamp + p->max_shift;
   const int64_t total = pitch * p->nchans;
+  // the tiled float kernel addresses its input with 32-bit byte offsets;
+  // larger float inputs take the direct kernel
+  if (v > 0 && p->dtype == DEDISP_F32 && !f32_offsets_fit(p, nsamp)) v = 0;
   if (v == 0) {
     const int64_t tblocks = (nsamp + 255) / 256;
     const int64_t nblocks = tblocks * p->ndm;
@@ -778,10 +1048,20 @@ int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, T
   a.pitch = pitch;
   a.total4 = total & ~static_cast<int64_t>(3);
   a.ntail = static_cast<int>(total - a.total4);
+  a.max_shift = p->max_shift;
   a.out = out;
   a.nsamp = nsamp;
   a.shift = dt->shift;
   a.win = reinterpret_cast<const int32_t*>(win);
+  a.geo = nullptr;
+  if (p->dtype == DEDISP_F32) {
+    // the float kernel addresses the input with 32-bit byte offsets
+    if (!f32_offsets_fit(p, nsamp)) return DEDISP_ERR_INVALID_ARG;
+    const int2* geo = nullptr;
+    st = device_geo(p, dev, var.shape.dms(), var.shape.samples(), static_cast<int>(pitch & 3), &geo);
+    if (st != DEDISP_OK) return st;
+    a.geo = reinterpret_cast<const int32_t*>(geo);
+  }
   a.ndm = p->ndm;
   a.ndm_pad = p->ndm_pad;
   a.nchans = p->nchans;
@@ -798,7 +1078,7 @@ int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, T
   // a multiple of 8 groups, so that every XCD's run of blocks is whole groups
   const int64_t nblocks = (n_groups + 7) / 8 * 8 * a.gd * a.gt;
   if (nblocks > INT32_MAX) return DEDISP_ERR_INVALID_ARG;
-  *lds_out = 2 * static_cast<size_t>(zunits) * (p->dtype == DEDISP_U8 ? 8 : 16);
+  *lds_out = 2 * static_cast<size_t>(var.cg) * zunits * (p->dtype == DEDISP_U8 ? 8 : 16);
   *nblocks_out = nblocks;
   *threads_out = var.shape.threads();
   return DEDISP_OK;
@@ -823,7 +1103,7 @@ int allow_large_lds(const void* fn) {
   return DEDISP_OK;
 }
 
-int prepare(dedisp_plan p, int v) {
+int prepare(dedisp_plan p, int v, int64_t nsamp) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
@@ -833,6 +1113,12 @@ int prepare(dedisp_plan p, int v) {
   const int2* w = nullptr;
   st = device_windows(p, dev, variant_shape(v).dms(), &w);
   if (st != DEDISP_OK) return st;
+  if (p->dtype == DEDISP_F32) {
+    const int2* g = nullptr;
+    st = device_geo(p, dev, variant_shape(v).dms(), variant_shape(v).samples(),
+                    static_cast<int>((nsamp + p->max_shift) & 3), &g);
+    if (st != DEDISP_OK) return st;
+  }
   return allow_large_lds(kVariants[v - 1].fn[p->dtype]);
 }
 

@@ -69,6 +69,7 @@ extern "C" int dedisp_plan_destroy(dedisp_plan p) {
     if (hipSetDevice(kv.first) != hipSuccess) continue;
     if (kv.second.shift) (void)hipFree(kv.second.shift);
     for (auto& w : kv.second.windows) (void)hipFree(w.second);
+    for (auto& w : kv.second.geo) (void)hipFree(w.second);
   }
   if (dev0 >= 0) (void)hipSetDevice(dev0);
   delete p;
@@ -147,8 +148,10 @@ int device_tables(dedisp_plan p, int device, DeviceTables** out) {
   DeviceTables& t = p->dev[device];
   if (t.shift == nullptr) {
     // Rows padded to a multiple of 64 trials, pad entries repeat the last trial
-    // so that every padded read stays inside the window of its tile.
-    std::vector<int32_t> padded(static_cast<size_t>(p->nchans) * p->ndm_pad);
+    // so that every padded read stays inside the window of its tile.  Two
+    // rows of zeros follow the last channel: kernels read the delays of the
+    // next channel ahead without a bounds check.
+    std::vector<int32_t> padded(static_cast<size_t>(p->nchans + 2) * p->ndm_pad, 0);
     for (int c = 0; c < p->nchans; ++c) {
       const int32_t* src = p->shift.data() + static_cast<size_t>(c) * p->ndm;
       int32_t* dst = padded.data() + static_cast<size_t>(c) * p->ndm_pad;
@@ -184,6 +187,39 @@ int device_windows(dedisp_plan p, int device, int dms_per_tile, const int2** out
       return hip_status(e);
     }
     it = t.windows.emplace(dms_per_tile, dptr).first;
+  }
+  *out = it->second;
+  return DEDISP_OK;
+}
+
+int device_geo(dedisp_plan p, int device, int dms_per_tile, int samples, int pitch_mod4, const int2** out) {
+  const std::vector<int2>& hw = host_windows(p, dms_per_tile);
+  const int64_t key = (static_cast<int64_t>(dms_per_tile) << 40) | (static_cast<int64_t>(samples) << 8) | pitch_mod4;
+  std::lock_guard<std::mutex> g(p->mu);
+  DeviceTables& t = p->dev[device];
+  auto it = t.geo.find(key);
+  if (it == t.geo.end()) {
+    const int ntiles = static_cast<int>(hw.size() / p->nchans);
+    std::vector<int2> geo(hw.size());
+    for (int tile = 0; tile < ntiles; ++tile)
+      for (int c = 0; c < p->nchans; ++c) {
+        const int2 w = hw[static_cast<size_t>(tile) * p->nchans + c];
+        // alignment of the window start c*pitch + t0 + lo (t0 is a multiple of 4)
+        const int mis = static_cast<int>((static_cast<int64_t>(c) * pitch_mod4 + w.x) & 3);
+        geo[static_cast<size_t>(tile) * p->nchans + c] = make_int2(mis - w.x, (mis + (w.y - w.x) + samples + 7) >> 2);
+      }
+    // entries past the last (tile, channel) are zero: kernels read the window
+    // of channels ahead without a bounds check
+    geo.resize(geo.size() + kGeoPad, make_int2(0, 0));
+    int2* dptr = nullptr;
+    hipError_t e = hipMalloc(&dptr, geo.size() * sizeof(int2));
+    if (e != hipSuccess) return hip_status(e);
+    e = hipMemcpy(dptr, geo.data(), geo.size() * sizeof(int2), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(dptr);
+      return hip_status(e);
+    }
+    it = t.geo.emplace(key, dptr).first;
   }
   *out = it->second;
   return DEDISP_OK;
