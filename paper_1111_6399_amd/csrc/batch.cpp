@@ -10,7 +10,10 @@
 // with a stream-ordered copy when the caller's pointers change, so the graph
 // itself never needs to be rebuilt for new buffers.  Beams that the chosen
 // variant cannot stage (delay spread too wide) run as their own launches,
-// captured in the same graph.
+// captured in the same graph.  8-bit and half inputs are widened into
+// buffers the batch owns (one per such beam) by one kernel at the head of the
+// graph, which reads its jobs from a device table refreshed like the argument
+// table.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,7 +37,11 @@ struct dedisp_batch_s {
   int64_t* d_item_end = nullptr;
   int* d_dtype = nullptr;
   unsigned long long* d_counter = nullptr;
+  dedisp::WidenJob* d_jobs = nullptr;
+  int njobs = 0;
+  std::vector<void*> ws;                // widened input per beam (8-bit and half beams)
   dedisp::TiledArgs* h_args = nullptr;  // pinned staging, two halves
+  dedisp::WidenJob* h_jobs = nullptr;   // pinned staging, two halves
   int h_half = 0;
   hipEvent_t h_done[2] = {nullptr, nullptr};
   hipStream_t capture = nullptr;
@@ -65,6 +72,14 @@ int free_device(dedisp_batch b) {
   if (b->d_dtype) (void)hipFree(b->d_dtype);
   if (b->d_counter) (void)hipFree(b->d_counter);
   if (b->h_args) (void)hipHostFree(b->h_args);
+  if (b->d_jobs) (void)hipFree(b->d_jobs);
+  if (b->h_jobs) (void)hipHostFree(b->h_jobs);
+  for (void* w : b->ws)
+    if (w) (void)hipFree(w);
+  b->ws.clear();
+  b->d_jobs = nullptr;
+  b->h_jobs = nullptr;
+  b->njobs = 0;
   for (auto& e : b->h_done)
     if (e) (void)hipEventDestroy(e);
   if (b->capture) (void)hipStreamDestroy(b->capture);
@@ -117,18 +132,31 @@ int pick_variant(dedisp_batch b) {
   return best_work > 0.0 ? best : -1;
 }
 
-// Fill the argument table for the current pointers into the next pinned half.
+int64_t total_samples(dedisp_batch b, int i) {
+  return (b->nsamps[i] + b->plans[i]->max_shift) * b->plans[i]->nchans;
+}
+
+// Fill the argument and widening tables for the current pointers into the
+// next pinned half.
 int build_args(dedisp_batch b, const void* const* ins, void* const* outs, dedisp::TiledArgs** host,
                std::vector<int64_t>* ends, std::vector<int>* dtypes) {
   dedisp::TiledArgs* h = b->h_args + b->h_half * b->nbeams;
+  dedisp::WidenJob* hj = b->h_jobs + b->h_half * b->nbeams;
   int64_t acc = 0;
   size_t lds = 0;
+  b->njobs = 0;
   for (size_t k = 0; k < b->order.size(); ++k) {
     const int i = b->order[k];
     size_t l = 0;
     int64_t nblocks = 0;
     int threads = 0;
-    const int st = dedisp::tiled_args(b->plans[i], b->variant, ins[i], outs[i], b->nsamps[i], &h[k], &l, &nblocks,
+    const void* src = ins[i];
+    if (b->ws[i] != nullptr) {
+      const int64_t n = total_samples(b, i);
+      hj[b->njobs++] = dedisp::WidenJob{ins[i], b->ws[i], n, dedisp::widened_samples(n), b->plans[i]->dtype};
+      src = b->ws[i];
+    }
+    const int st = dedisp::tiled_args(b->plans[i], b->variant, src, outs[i], b->nsamps[i], &h[k], &l, &nblocks,
                                       &threads);
     if (st != DEDISP_OK) return st;
     lds = std::max(lds, l);
@@ -154,6 +182,17 @@ int setup_device(dedisp_batch b, int dev, const void* const* ins, void* const* o
   if ((e = hipMalloc(&b->d_counter, sizeof(unsigned long long))) != hipSuccess) return DEDISP_HIP_STATUS(e);
   if ((e = hipHostMalloc(&b->h_args, 2 * std::max(1, b->nbeams) * sizeof(dedisp::TiledArgs))) != hipSuccess)
     return DEDISP_HIP_STATUS(e);
+  if ((e = hipHostMalloc(&b->h_jobs, 2 * std::max(1, b->nbeams) * sizeof(dedisp::WidenJob))) != hipSuccess)
+    return DEDISP_HIP_STATUS(e);
+  if ((e = hipMalloc(&b->d_jobs, std::max(1, b->nbeams) * sizeof(dedisp::WidenJob))) != hipSuccess)
+    return DEDISP_HIP_STATUS(e);
+  b->ws.assign(b->nbeams, nullptr);
+  for (int i = 0; i < b->nbeams; ++i) {
+    const int dt = b->plans[i]->dtype;
+    if (dt == DEDISP_F32) continue;
+    const size_t bytes = static_cast<size_t>(dedisp::widened_samples(total_samples(b, i))) * dedisp::staged_size(dt);
+    if ((e = hipMalloc(&b->ws[i], bytes)) != hipSuccess) return DEDISP_HIP_STATUS(e);
+  }
   for (auto& ev : b->h_done)
     if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return DEDISP_HIP_STATUS(e);
   if ((e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking)) != hipSuccess) return DEDISP_HIP_STATUS(e);
@@ -169,6 +208,10 @@ int setup_device(dedisp_batch b, int dev, const void* const* ins, void* const* o
   if ((e = hipMemcpy(b->d_item_end, ends.data(), ends.size() * sizeof(int64_t), hipMemcpyHostToDevice)) != hipSuccess)
     return DEDISP_HIP_STATUS(e);
   if ((e = hipMemcpy(b->d_dtype, dtypes.data(), dtypes.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+    return DEDISP_HIP_STATUS(e);
+  if (b->njobs > 0 &&
+      (e = hipMemcpy(b->d_jobs, b->h_jobs + b->h_half * b->nbeams, b->njobs * sizeof(dedisp::WidenJob),
+                     hipMemcpyHostToDevice)) != hipSuccess)
     return DEDISP_HIP_STATUS(e);
   return DEDISP_OK;
 }
@@ -202,6 +245,10 @@ int build_graph(dedisp_batch b, const void* const* ins, void* const* outs) {
   if (!b->order.empty()) {
     void* rargs[] = {&b->d_counter};
     e = hipLaunchKernel(dedisp::reset_kernel(), dim3(1), dim3(1), rargs, 0, b->capture);
+    if (e == hipSuccess && b->njobs > 0) {
+      st = dedisp::widen_jobs(b->d_jobs, b->njobs, b->capture);
+      if (st != DEDISP_OK) e = hipErrorUnknown;
+    }
     if (e == hipSuccess) {
       dedisp::BatchArgs ba;
       ba.beams = b->d_args;
@@ -213,11 +260,11 @@ int build_graph(dedisp_batch b, const void* const* ins, void* const* outs) {
       void* kargs[] = {&ba};
       e = hipLaunchKernel(fn, dim3(b->grid), dim3(b->threads), kargs, b->lds, b->capture);
     }
-    if (e != hipSuccess) st = DEDISP_HIP_STATUS(e);
+    if (e != hipSuccess && st == DEDISP_OK) st = DEDISP_HIP_STATUS(e);
   }
   for (size_t k = 0; k < b->solo.size() && st == DEDISP_OK; ++k) {
     const int i = b->solo[k];
-    st = dedisp::launch(b->plans[i], b->solo_variant[k], ins[i], outs[i], b->nsamps[i], b->capture);
+    st = dedisp::launch(b->plans[i], b->solo_variant[k], ins[i], outs[i], b->nsamps[i], b->capture, b->ws[i]);
   }
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(b->capture, &g);
@@ -308,6 +355,9 @@ extern "C" int dedisp_batch_execute(dedisp_batch b, const void* const* ins, void
       st = build_args(b, ins, outs, &h, nullptr, nullptr);
       if (st != DEDISP_OK) return st;
       e = hipMemcpyAsync(b->d_args, h, b->order.size() * sizeof(dedisp::TiledArgs), hipMemcpyHostToDevice, stream);
+      if (e == hipSuccess && b->njobs > 0)
+        e = hipMemcpyAsync(b->d_jobs, b->h_jobs + b->h_half * b->nbeams, b->njobs * sizeof(dedisp::WidenJob),
+                           hipMemcpyHostToDevice, stream);
       if (e == hipSuccess) e = hipEventRecord(b->h_done[b->h_half], stream);
       if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
     }

@@ -17,12 +17,18 @@ namespace dedisp {
 
 // Float sums are accumulated in blocks of this many channels (see dedisp.h).
 constexpr int kChanBlock = 32;
-// Zero entries after the window-geometry table (covers the channels a kernel
-// reads ahead past the last one).
-constexpr int kGeoPad = 64;
+// Zero entries after each trial tile's row of the window-geometry table
+// (covers the channels a kernel reads ahead past the last one).
+constexpr int kGeoPad = 16;
+// Zero rows after the last channel of the device delay table (covers the
+// channels a kernel reads ahead past the last one).
+constexpr int kShiftPadRows = 16;
 
 
 inline size_t dtype_size(int dtype) { return dtype == DEDISP_U8 ? 1 : dtype == DEDISP_F16 ? 2 : 4; }
+// Bytes per sample the tiled kernels read: 8-bit input widened to 16 bits,
+// half input widened to float.
+inline int64_t staged_size(int dtype) { return dtype == DEDISP_U8 ? 2 : 4; }
 inline size_t out_size(int) { return 4; }
 
 // Shape of a tiled kernel variant.
@@ -55,7 +61,7 @@ struct TiledArgs {
   int64_t nsamp;
   const int32_t* shift;  // [nchans][ndm_pad]
   const int32_t* win;    // [n_dm_tiles][nchans][2] (min, max) delay
-  const int32_t* geo;    // [n_dm_tiles][nchans][2] (e, n4): window start and length (see device_geo)
+  const int32_t* geo;    // [n_dm_tiles][nchans + kGeoPad][2] (e, n4): window start and length (see device_geo)
   int ndm, ndm_pad, nchans;
   int zunits;  // 4-sample units per LDS slot (one channel of a stage)
   int n_dm_tiles, n_t_tiles;
@@ -63,6 +69,15 @@ struct TiledArgs {
   int n_dm_groups;  // groups along trials
   int ntail;        // samples past total4 (0..3)
   int max_shift;    // largest delay of the plan
+};
+
+// One input of a batch to widen before the persistent kernel (8-bit to 16
+// bits or half to float, padded with zeros to npad samples).
+struct WidenJob {
+  const void* in;
+  void* ws;
+  int64_t n, npad;
+  int dtype;
 };
 
 struct BatchArgs {
@@ -99,11 +114,12 @@ int device_tables(dedisp_plan p, int device, DeviceTables** out);
 int device_windows(dedisp_plan p, int device, int dms_per_tile, const int2** out);
 const std::vector<int2>& host_windows(dedisp_plan p, int dms_per_tile);
 // Window geometry of every (trial tile, channel) for tiles of `samples`
-// samples (a multiple of 4) and rows whose length is `pitch_mod4` modulo 4:
-// e = (window start alignment) - (minimum delay), so that the window of a tile
-// starting at sample t0 begins at absolute sample c*pitch + t0 - e (a multiple
-// of 4), and n4 = 4-sample units the window spans.
-int device_geo(dedisp_plan p, int device, int dms_per_tile, int samples, int pitch_mod4, const int2** out);
+// samples (a multiple of align, 4 or 8) and rows whose length is `pitch_mod`
+// modulo align: e = (window start alignment) - (minimum delay), so that the
+// window of a tile starting at sample t0 begins at absolute sample
+// c*pitch + t0 - e (a multiple of align), and n4 = 4-sample units the window
+// spans.
+int device_geo(dedisp_plan p, int device, int dms_per_tile, int samples, int align, int pitch_mod, const int2** out);
 
 // Kernel registry (kernels.hip).
 int variant_count();
@@ -113,8 +129,17 @@ TileShape variant_shape(int v);   // v >= 1
 bool variant_fits(dedisp_plan p, int v);
 int default_variant(dedisp_plan p);
 
-// Launch one plan's kernel over the whole problem.
-int launch(dedisp_plan p, int variant, const void* in, void* out, int64_t nsamp, hipStream_t s);
+// Launch one plan's kernel over the whole problem.  8-bit and half input is
+// widened into `ws` (widened_samples(total) * staged_size bytes) when given,
+// else into a stream-ordered allocation.
+int launch(dedisp_plan p, int variant, const void* in, void* out, int64_t nsamp, hipStream_t s, void* ws = nullptr);
+
+// 8-bit and half input are widened (to 16 bits and to float) before a tiled
+// launch, into a buffer of widened_samples(total) samples padded with zeros.
+int64_t widened_samples(int64_t total);
+int widen(int dtype, const void* in, void* ws, int64_t total, hipStream_t s);
+// Widen every job of a device table (launched from a batch graph).
+int widen_jobs(const WidenJob* jobs, int njobs, hipStream_t s);
 
 // Arguments, LDS bytes, block count and threads of a tiled launch of variant
 // v >= 1 (device tables are created on the current device if needed).

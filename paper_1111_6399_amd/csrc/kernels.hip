@@ -338,29 +338,24 @@ __device__ __forceinline__ void wait_vm() {
 // checked: reads past the end return zero without touching memory).
 __device__ __forceinline__ v4i buffer_words(const void* p, int64_t bytes) {
   const uint64_t a = reinterpret_cast<uint64_t>(p);
-  v4i w;
-  w.x = static_cast<int>(a & 0xffffffffu);
-  w.y = static_cast<int>((a >> 32) & 0xffffu);
-  w.z = static_cast<int>(bytes);
+  v4i w;  // wave-uniform by construction; made explicit for the scalar operands of inline assembly
+  w.x = __builtin_amdgcn_readfirstlane(static_cast<int>(a & 0xffffffffu));
+  w.y = __builtin_amdgcn_readfirstlane(static_cast<int>((a >> 32) & 0xffffu));
+  w.z = __builtin_amdgcn_readfirstlane(static_cast<int>(bytes));
   w.w = 0x00020000;
   return w;
 }
 
 // 16 bytes per lane from byte offset voff of the buffer straight into LDS at
-// lds + 16*lane, for the lanes whose unit index u is below n (the others do
-// nothing; the load still counts once in this wave's vector memory counter).
-__device__ __forceinline__ void lds_dma16(uint32_t lds, uint32_t voff, const v4i& rs, int n, uint32_t u) {
-  uint64_t save;
+// lds + 16*lane (every lane).
+__device__ __forceinline__ void lds_dma16_all(uint32_t lds, uint32_t voff, const v4i& rs) {
   asm volatile(
-      "v_cmp_gt_i32 vcc, %[n], %[u]\n\t"
-      "s_and_saveexec_b64 %[sv], vcc\n\t"
       "s_mov_b32 m0, %[lds]\n\t"
       "s_nop 0\n\t"
-      "buffer_load_dwordx4 %[vo], %[rs], 0 offen lds\n\t"
-      "s_mov_b64 exec, %[sv]"
-      : [sv] "=&s"(save)
-      : [n] "s"(n), [u] "v"(u), [lds] "s"(lds), [vo] "v"(voff), [rs] "s"(rs)
-      : "vcc", "memory");
+      "buffer_load_dwordx4 %[vo], %[rs], 0 offen lds"
+      :
+      : [lds] "s"(lds), [vo] "v"(voff), [rs] "s"(rs)
+      : "memory");
 }
 
 // Workgroup barrier after this wave's LDS writes have completed.  Writes that
@@ -369,399 +364,212 @@ __device__ __forceinline__ void lds_barrier_asm() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-// Float input, staged by loads that write LDS directly (no registers): a ring
-// of NS = 2*CG channel slots, the windows of the next NS-1 channels in flight
-// while a channel is accumulated.  A slot holds R*NT units; wave w loads units
-// [r*NT + 64w, r*NT + 64w + 64) of a window with its r-th load (16 bytes per
-// lane).  Lanes past the window are masked off except lane 0, so that every
-// wave issues exactly R loads per channel and waits for its loads of the
-// channel about to be used with a constant count; a barrier then makes every
-// wave's loads visible.  One buffer descriptor covers the whole input (32-bit
-// byte offsets).  Window start and length come from a table built on the host
-// per (trial tile, channel); the scalar loads of the table and of the delays
-// run a channel ahead, and both tables are padded so that reading past the
-// last channel needs no check.
-template <int DW, int KS, int WD, int WT, int R, int CG>
-__device__ __forceinline__ void tile_f32_dma(const TiledArgs& a, int dm_tile, int t_tile) {
-  constexpr int NT = 64 * WD * WT;
+// Tile kernel body.  The input is staged by loads that write LDS directly
+// (no registers).  Float input (and half input widened to float beforehand)
+// is staged as float32, 16 bytes per 4 samples; 8-bit input, widened
+// beforehand to 16 bits, is staged as pairs of samples in the two 16-bit
+// halves of a word (8 bytes per 4 samples), so that one 32-bit add
+// accumulates two samples exactly (a half holds 256 channels of 255 before it
+// could carry).
+//
+// Channels are processed in stages of CG, two stages alternating in LDS (one
+// slot per channel).  The loads of a channel are issued by one group of NW/4
+// waves, the groups taking turns channel by channel; a group's waves split
+// the channel's window into runs of 1 KB (16 bytes per lane) and issue
+// exactly the runs the window needs.  A group issues the loads of a channel
+// of the next stage right after the barrier that frees its slot, and before
+// the barrier of that stage waits for all of its outstanding loads (it has no
+// other loads in flight: its next channel is at least 4 channels later, in a
+// later stage); the barrier then makes every load of the stage visible.  Only
+// the issuing waves do this work, so the scalar cost of staging is paid once
+// per run instead of once per wave.  One buffer descriptor covers the whole
+// input (32-bit byte offsets).  Window start and length come from a table
+// built on the host per (trial tile, channel); both it and the delay table
+// are padded so that reading a stage past the last channel needs no check.
+//
+// A (channel, trial) block reads its samples with aligned 64-bit reads,
+// several blocks of reads in flight.  Lanes 0-62 own the output samples; lane
+// 63 only supplies its neighbour when the block's window position is not a
+// multiple of the word pair.  8-bit blocks have a second alignment, the
+// sample within a word: odd positions accumulate into a second set of words
+// that holds every sum one sample earlier, and the two sets are combined into
+// 32-bit totals every 256 channels.  Float sums: channels ascending, summed in
+// blocks of kChanBlock into a partial that is then added to the total (the
+// same order in every variant).
+template <bool kPairs, int DW, int KS, int WD, int WT, int CG>
+__device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_tile) {
+  constexpr int NW = WD * WT;
   constexpr int SPW = 126 * KS;
   constexpr int T = SPW * WT;
-  constexpr int NR = KS;
-  constexpr int NS = 2 * CG;
-  constexpr int D = 2;
+  constexpr int NR = kPairs ? KS / 2 : KS;  // 64-bit LDS reads per lane and block
+  constexpr int ES = kPairs ? 2 : 4;        // bytes per staged sample
+  constexpr int UB = 4 * ES;                // LDS bytes per 4-sample unit
+  constexpr int G = 4;                      // issuing groups
+  constexpr int WPG = NW / G;               // waves per group
+  constexpr int NB = CG * DW;               // (channel, trial) blocks per stage
+  constexpr int D = (3 - 1) * NR <= 15 ? 3 : 2;  // blocks with reads in flight
+  constexpr int FLUSH = kPairs ? 256 : kChanBlock;
   static_assert(KS % 2 == 0 && (D - 1) * NR <= 15, "tile shape");
-  static_assert(NS >= 2 && kChanBlock % NS == 0, "ring size");
-  static_assert((NS - 2) * R <= 63, "vector memory counter");
+  static_assert(NW % G == 0 && CG <= G && FLUSH % CG == 0, "stage shape");
   extern __shared__ float4 lds4[];
-  const float* __restrict__ in = static_cast<const float*>(a.in);
-  typedef __attribute__((address_space(3))) char lds_char;
-  lds_char* l3 = (lds_char*)(__attribute__((address_space(3))) void*)lds4;
 
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
   const int wd = wave % WD;
   const int wt = wave / WD;
-  const int t0 = t_tile * T;  // the input is below 2^32 bytes, so are these indices
+  const int grp = wave / WPG;   // issuing group of this wave
+  const int gq = wave % WPG;    // rank inside it
+  const int t0 = t_tile * T;    // the input is below 2^32 bytes, so are these indices
   const int dw0 = dm_tile * (DW * WD) + wd * DW;
   const int tw = wt * SPW;
   const int nchans = a.nchans;
   const int pitch = static_cast<int>(a.pitch);
-  const uint32_t slot_bytes = static_cast<uint32_t>(a.zunits) * 16u;
-  const uint32_t vlane = lds_addr(lds4) + 8u * static_cast<uint32_t>(lane);
+  const uint32_t slot_bytes = static_cast<uint32_t>(a.zunits) * UB;
+  const uint32_t lds0 = lds_addr(lds4);
+  const uint32_t vlane = lds0 + 8u * static_cast<uint32_t>(lane);
+  const v4i rs = buffer_words(a.in, a.total4 * ES);
+  const uint32_t lane16 = 16u * static_cast<uint32_t>(lane);
+  cint32* geo = (cint32*)(a.geo) + 2 * static_cast<int64_t>(dm_tile) * (nchans + kGeoPad);
 
+  // The last 1-3 samples of a float input (past the last whole group of 4)
+  // are read once here; the window holding them patches them in.  (Widened
+  // inputs are padded to whole groups.)
   float tail[3] = {0.f, 0.f, 0.f};
+  int c_tail = nchans;  // first channel whose window can reach them
+  if (!kPairs && a.ntail > 0) {
+    const float* inf = static_cast<const float*>(a.in);
 #pragma unroll
-  for (int k = 0; k < 3; ++k)
-    if (k < a.ntail) tail[k] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(in[a.total4 + k])));
-  // First channel whose window can reach the partial last group of the input
-  // (a window ends before c*pitch + t0 + max_shift + T + 10).
-  int c_tail;
-  {
+    for (int k = 0; k < 3; ++k)
+      if (k < a.ntail) tail[k] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(inf[a.total4 + k])));
+    // a window ends before c*pitch + t0 + max_shift + T + 10
     const int64_t lim = a.total4 - t0 - a.max_shift - (T + 10);
     c_tail = lim < 0 ? 0 : static_cast<int>(lim / a.pitch) + 1;
   }
 
-  // Loads of the window (start e, length n4 units) whose channel row starts at
-  // byte 4*(row + t0) = cbase, into slot s.  A load whose lanes are all past
-  // the window still issues (with no lane active it counts as done without
-  // touching memory or LDS), so the count per channel is always R.
-  uint32_t cbase = 4u * static_cast<uint32_t>(t0);
-  uint32_t ur[R], uoff[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    ur[r] = static_cast<uint32_t>(tid + r * NT);
-    uoff[r] = 16u * ur[r];
-  }
-  const v4i rs = buffer_words(in, a.total4 * 4);
-  const uint32_t ldsw = lds_addr(lds4) + 16u * static_cast<uint32_t>(64 * wave);
-  auto load = [&](int s, int e, int n4) {
-    const uint32_t base = cbase - 4u * static_cast<uint32_t>(e);
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-      lds_dma16(ldsw + s * slot_bytes + 16u * (r * NT), base + uoff[r], rs, n4, ur[r]);
-    cbase += 4u * static_cast<uint32_t>(pitch);
+  // This wave's share of the loads of channel c (window start e, length n4)
+  // if its group issues c: runs gq, gq + WPG, ... of the window, into LDS byte
+  // offset slot.
+  auto issue = [&](int c, int e, int n4, uint32_t slot) {
+    if ((c % G) != grp || c >= nchans) return;
+    const uint32_t base = ES * static_cast<uint32_t>(c * pitch + t0 - e) + lane16;
+    const int nruns = (n4 * UB + 1023) >> 10;
+    for (int i = gq; i < nruns; i += WPG) lds_dma16_all(lds0 + slot + 1024u * i, base + 1024u * i, rs);
   };
-
-  float part[DW][2 * NR];
-  float tot[DW][2 * NR];
-#pragma unroll
-  for (int j = 0; j < DW; ++j)
-#pragma unroll
-    for (int k = 0; k < 2 * NR; ++k) part[j][k] = tot[j][k] = 0.f;
-
-  cint32* gp = (cint32*)(a.geo) + 2 * static_cast<int64_t>(dm_tile) * nchans;  // next (e, n4) to read
-  int eq[NS], nq[NS];  // window of the channel in each slot
-#pragma unroll
-  for (int u = 0; u < NS - 1; ++u) {
-    eq[u] = gp[0];
-    nq[u] = gp[1];
-    gp += 2;
-    load(u, eq[u], nq[u]);
-  }
-  int en = gp[0], nn = gp[1];  // window of the next channel to load
-  gp += 2;
-  cint32* sp = (cint32*)(a.shift) + dw0;  // delays of the channel about to be accumulated
-  int sh[DW];
-#pragma unroll
-  for (int j = 0; j < DW; ++j) sh[j] = sp[j];
-  sp += a.ndm_pad;
-
-  for (int cb = 0; cb < nchans; cb += NS) {
-#pragma unroll
-    for (int u = 0; u < NS; ++u) {
-      const int c = cb + u;
-      if (c >= nchans) break;
-      wait_vm<(NS - 2) * R>();  // this wave's loads of channel c are in LDS
-      if (c >= c_tail) {
-        const int64_t a0 = static_cast<int64_t>(c) * pitch + t0 - eq[u];
-        if (a0 + 4 * static_cast<int64_t>(nq[u]) > a.total4) {  // the window holds the partial last group
-          const int itail = static_cast<int>(a.total4 - a0) >> 2;
-          if (tid == itail % NT && itail / NT < R)
-            *reinterpret_cast<float4*>(reinterpret_cast<char*>(lds4) + u * slot_bytes +
-                                       16 * ((itail / NT) * NT + 64 * (itail % NT / 64)) + 16 * (itail % 64)) =
-                make_float4(tail[0], tail[1], tail[2], 0.f);
-        }
-      }
-      lds_barrier_asm();
-      const int eo = eq[u] + tw;
-      uint32_t ba[DW];
-      int pb[DW];
-#pragma unroll
-      for (int j = 0; j < DW; ++j) {
-        pb[j] = sh[j] + eo;
-        ba[j] = vlane + (u * slot_bytes + 4u * static_cast<uint32_t>(pb[j] & ~1));
-      }
-      v2u rb[D][NR];
-      lds_reads<NR>(ba[0], rb[0]);
-      // the slot of channel c-1 is free: load channel c+NS-1 into it, then
-      // start the scalar loads of the next channel (used one channel later)
-      {
-        const int un = (u + NS - 1) % NS;
-        eq[un] = en;
-        nq[un] = nn;
-        load(un, en, nn);
-        en = gp[0];
-        nn = gp[1];
-        gp += 2;
-      }
-      int shn[DW];
-#pragma unroll
-      for (int j = 0; j < DW; ++j) shn[j] = sp[j];
-      sp += a.ndm_pad;
-#pragma unroll
-      for (int j = 0; j < DW; ++j) {
-        if (j + 1 < DW) {
-          lds_reads<NR>(ba[j + 1], rb[(j + 1) % D]);
-          lds_wait<NR>();
-        } else {
-          lds_wait<0>();
-        }
-        TrialAdds<NR>::f32(part[j], rb[j % D], pb[j]);
-      }
-      if (u == NS - 1 && ((cb + NS) % kChanBlock) == 0) {
-#pragma unroll
-        for (int j = 0; j < DW; ++j)
-#pragma unroll
-          for (int k = 0; k < 2 * NR; ++k) {
-            tot[j][k] += part[j][k];
-            part[j][k] = 0.f;
-          }
-      }
-#pragma unroll
-      for (int j = 0; j < DW; ++j) sh[j] = shn[j];
-    }
-  }
-  // the channels after the last whole block of kChanBlock
-#pragma unroll
-  for (int j = 0; j < DW; ++j)
-#pragma unroll
-    for (int k = 0; k < 2 * NR; ++k) tot[j][k] += part[j][k];
-  wait_vm<0>();  // no load may still be writing LDS when the workgroup ends
-
-  if (lane == 63) return;  // the halo lane owns no output
-  const int64_t nsamp = a.nsamp;
-#pragma unroll
-  for (int j = 0; j < DW; ++j) {
-    const int d = dw0 + j;
-    if (d >= a.ndm) break;
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      const int64_t t = static_cast<int64_t>(t0) + tw + 2 * lane + 126 * k;
-      float* o = static_cast<float*>(a.out) + d * nsamp + t;
-      if (t + 1 < nsamp) {
-        const float2 w2 = make_float2(tot[j][2 * k], tot[j][2 * k + 1]);
-        __builtin_memcpy(o, &w2, 8);
-      } else if (t < nsamp) {
-        *o = tot[j][2 * k];
-      }
-    }
-  }
-}
-
-// Scalar geometry of one channel's window in a stage.
-struct Win {
-  int64_t a0;  // first staged sample (absolute index, a multiple of 4)
-  int64_t rem; // samples from a0 to the end of the whole groups of 4 of the input
-  int n4;      // 4-sample units staged
-  int off;     // window index of the wave's first output sample at delay 0
-};
-
-// Workgroup tile: WD*DW trials x WT*126*KS samples.  Wave (wd, wt) owns DW
-// trials and 126*KS consecutive samples of each.
-//
-// Channels are processed in stages of CG.  For a stage the workgroup stages,
-// per channel, the window of input the tile needs into LDS (one slot per
-// channel, two stages alternate), with one barrier per stage; the global
-// loads of the next stage are in flight in registers meanwhile (R 4-sample
-// units per thread and channel).  Float and half input is staged as float32
-// (16 bytes per 4 samples); 8-bit input as pairs of samples in the two 16-bit
-// halves of a word (8 bytes per 4 samples), so that one 32-bit add
-// accumulates two samples exactly (a half holds 256 channels of 255 before
-// it could carry).
-//
-// A (channel, trial) block reads its samples with aligned 64-bit reads.
-// Lanes 0-62 own the output samples; lane 63 only supplies its neighbour when
-// the block's window position is not a multiple of the word pair (float: odd
-// sample; 8-bit: odd word).  8-bit input has a second alignment, the sample
-// within a word: odd positions accumulate into a second set of words that
-// holds every sum one sample earlier, and the two sets are combined into
-// 32-bit totals every 256 channels.  The delay and the alignment only enter
-// a wave-uniform address and a uniform branch.  The reads of the next blocks
-// of the stage are in flight while a block is added.
-//
-// Float sums: channels ascending, summed in blocks of kChanBlock into a
-// partial that is then added to the total (the same order in every variant).
-template <typename In, int DW, int KS, int WD, int WT, int R, int CG>
-__device__ __forceinline__ void tile_body(const TiledArgs& a, int dm_tile, int t_tile) {
-  if constexpr (std::is_same<In, float>::value) {
-    tile_f32_dma<DW, KS, WD, WT, R, CG>(a, dm_tile, t_tile);
-    return;
-  }
-  constexpr bool kU8 = sizeof(In) == 1;
-  constexpr int NT = 64 * WD * WT;
-  constexpr int SPW = 126 * KS;          // output samples per wave and trial
-  constexpr int T = SPW * WT;            // output samples per tile
-  constexpr int NR = kU8 ? KS / 2 : KS;  // 64-bit reads per lane and block
-  constexpr int UB = kU8 ? 8 : 16;       // LDS bytes per 4-sample unit
-  constexpr int NB = CG * DW;            // (channel, trial) blocks per stage
-  constexpr int D = (3 - 1) * NR <= 15 ? 3 : 2;  // blocks with reads in flight
-  static_assert(KS % 2 == 0, "KS must be even");
-  static_assert((D - 1) * NR <= 15, "the LDS wait counter holds at most 15");
-  static_assert((kU8 ? 256 : kChanBlock) % CG == 0, "a stage must not straddle a flush");
-  extern __shared__ float4 lds4[];
-  const In* __restrict__ in = static_cast<const In*>(a.in);
-
-  const int tid = threadIdx.x;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int lane = tid & 63;
-  const int wd = wave % WD;
-  const int wt = wave / WD;
-  const int64_t t0 = static_cast<int64_t>(t_tile) * T;
-  const int dw0 = dm_tile * (DW * WD) + wd * DW;
-  const int tw = wt * SPW;
-  cint32* wrow = (cint32*)(a.win) + 2 * static_cast<int64_t>(dm_tile) * a.nchans;
-  cint32* srow = (cint32*)(a.shift) + dw0;
-  const int nchans = a.nchans;
-  const int nlast = nchans - 1;
-  const uint32_t slot_bytes = static_cast<uint32_t>(a.zunits) * UB;
-  const uint32_t lds0 = lds_addr(lds4);
-  const uint32_t vlane = lds0 + 8u * static_cast<uint32_t>(lane);
-
-  // The last 1-3 samples of the input (past the last whole group of 4) are
-  // read once here; a window that reaches them patches them in.
-  uint32_t tail[3] = {0u, 0u, 0u};
-#pragma unroll
-  for (int k = 0; k < 3; ++k)
-    if (k < a.ntail) {
-      if constexpr (kU8)
-        tail[k] = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(in[a.total4 + k])));
-      else
-        tail[k] = static_cast<uint32_t>(
-            __builtin_amdgcn_readfirstlane(__float_as_int(Elem<In>::get(in, a.total4 + k))));
-    }
-
-  // Window of channel c (clamped to the last channel past the end).
-  auto window = [&](int c) {
-    const int cc = min(c, nlast);
-    const int lo = wrow[2 * cc];
-    const int hi = wrow[2 * cc + 1];
-    Win g;
-    const int64_t w0 = static_cast<int64_t>(cc) * a.pitch + t0 + lo;
-    g.a0 = w0 & ~static_cast<int64_t>(3);
-    const int mis = static_cast<int>(w0) & 3;
-    g.n4 = (mis + (hi - lo) + (T + 7)) >> 2;
-    g.off = mis + tw - lo;
-    g.rem = a.total4 - g.a0;
-    return g;
-  };
-
-  // Global loads of one channel's window.  Past the last channel the same
-  // instructions run against an empty range (they return zeros without
-  // touching memory), so every stage issues the same number of loads and the
-  // compiler's waits stay exact.
-  auto issue = [&](const Win& g, Raw<In>* rs, bool live) {
-    const int want = 4 * g.n4;
-    const int n = g.rem < want ? static_cast<int>(g.rem) : want;
-    const int num = live ? n * static_cast<int>(sizeof(In)) : 0;
-    const __amdgpu_buffer_rsrc_t rsrc =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<In*>(in + g.a0), 0, num, 0x00020000);
-#pragma unroll
-    for (int r = 0; r < R; ++r) rs[r] = load_raw<In>(rsrc, tid + r * NT);
-  };
-
-  // One staged unit (4 samples) in the LDS layout of the input type.
-  auto put = [&](uint32_t boff, int i, const Raw<In>& raw, bool is_tail) {
-    if constexpr (kU8) {
-      uint32_t w = raw.v;
-      uint2 u = make_uint2((w & 0xffu) | ((w & 0xff00u) << 8), ((w >> 16) & 0xffu) | ((w >> 8) & 0xff0000u));
-      if (is_tail) u = make_uint2(tail[0] | (tail[1] << 16), tail[2]);
-      reinterpret_cast<uint2*>(reinterpret_cast<char*>(lds4) + boff)[i] = u;
-    } else {
-      float4 v = to_float(raw);
-      if (is_tail) v = make_float4(__uint_as_float(tail[0]), __uint_as_float(tail[1]), __uint_as_float(tail[2]), 0.f);
-      reinterpret_cast<float4*>(reinterpret_cast<char*>(lds4) + boff)[i] = v;
-    }
+  // After this wave's loads of channel c landed: the partial last group of a
+  // float input, if the window holds it, is patched in by the wave and lane
+  // that loaded it.
+  auto patch = [&](int c, int e, int n4, uint32_t slot) {
+    if (kPairs || (c % G) != grp || c >= nchans || c < c_tail) return;
+    const int64_t a0 = static_cast<int64_t>(c) * pitch + t0 - e;
+    if (a0 + 4 * static_cast<int64_t>(n4) <= a.total4) return;
+    const int itail = static_cast<int>(a.total4 - a0) >> 2;
+    if (((itail >> 6) % WPG) == gq && lane == (itail & 63))
+      *reinterpret_cast<float4*>(reinterpret_cast<char*>(lds4) + slot + 16 * itail) =
+          make_float4(tail[0], tail[1], tail[2], 0.f);
   };
 
   // Accumulators.  Float: acc0 = partial of the current block of channels,
   // tot = total.  8-bit: acc0/acc1 = words of two 16-bit sums (acc1 one
   // sample earlier), tot = 32-bit totals.
   constexpr int NA = 2 * NR;
-  typedef typename std::conditional<kU8, uint32_t, float>::type Acc;
+  typedef typename std::conditional<kPairs, uint32_t, float>::type Acc;
   Acc acc0[DW][NA];
-  Acc acc1[DW][kU8 ? NA : 1];
-  Acc tot[DW][kU8 ? 4 * NR : NA];
+  Acc acc1[DW][kPairs ? NA : 1];
+  Acc tot[DW][kPairs ? 4 * NR : NA];
 #pragma unroll
   for (int j = 0; j < DW; ++j) {
 #pragma unroll
     for (int k = 0; k < NA; ++k) acc0[j][k] = 0;
 #pragma unroll
-    for (int k = 0; k < (kU8 ? NA : 1); ++k) acc1[j][k] = 0;
+    for (int k = 0; k < (kPairs ? NA : 1); ++k) acc1[j][k] = 0;
 #pragma unroll
-    for (int k = 0; k < (kU8 ? 4 * NR : NA); ++k) tot[j][k] = 0;
+    for (int k = 0; k < (kPairs ? 4 * NR : NA); ++k) tot[j][k] = 0;
   }
+  auto flush = [&]() {
+    if constexpr (kPairs) {
+#pragma unroll
+      for (int j = 0; j < DW; ++j)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+          const uint32_t ex = acc0[j][2 * k], ey = acc0[j][2 * k + 1];
+          const uint32_t ox = acc1[j][2 * k], oy = acc1[j][2 * k + 1];
+          const uint32_t oxn = from_next_lane(ox);
+          tot[j][4 * k + 0] += (ex & 0xffffu) + (ox >> 16);
+          tot[j][4 * k + 1] += (ex >> 16) + (oy & 0xffffu);
+          tot[j][4 * k + 2] += (ey & 0xffffu) + (oy >> 16);
+          tot[j][4 * k + 3] += (ey >> 16) + (oxn & 0xffffu);
+          acc0[j][2 * k] = acc0[j][2 * k + 1] = 0u;
+          acc1[j][2 * k] = acc1[j][2 * k + 1] = 0u;
+        }
+    } else {
+#pragma unroll
+      for (int j = 0; j < DW; ++j)
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+          tot[j][k] += acc0[j][k];
+          acc0[j][k] = 0.f;
+        }
+    }
+  };
 
-  Raw<In> raw[CG][R];
-  Win gq[CG];
+  // Scalar state, read a stage ahead (the tables are padded past the last
+  // channel): geometry of the current, next and following stage, delays of
+  // the current and next stage.
+  int ce[CG], cn[CG], ne[CG], nn[CG], fe[CG], fn[CG];
+  int sh[CG][DW], shn[CG][DW];
 #pragma unroll
   for (int u = 0; u < CG; ++u) {
-    gq[u] = window(u);
-    issue(gq[u], raw[u], u < nchans);
+    ce[u] = geo[2 * u];
+    cn[u] = geo[2 * u + 1];
+    ne[u] = geo[2 * (CG + u)];
+    nn[u] = geo[2 * (CG + u) + 1];
   }
+  cint32* gp = geo + 4 * CG;              // geometry of the stage after next
+  cint32* sp = (cint32*)(a.shift) + dw0;  // delays of the current stage
+#pragma unroll
+  for (int u = 0; u < CG; ++u)
+#pragma unroll
+    for (int j = 0; j < DW; ++j) sh[u][j] = sp[u * a.ndm_pad + j];
+  sp += CG * a.ndm_pad;
+#pragma unroll
+  for (int u = 0; u < CG; ++u) issue(u, ce[u], cn[u], u * slot_bytes);
 
   const int nstages = (nchans + CG - 1) / CG;
   for (int s = 0; s < nstages; ++s) {
     const int c0 = s * CG;
     const uint32_t sbase = (s & 1) ? CG * slot_bytes : 0u;
-    int off[CG];
-    int sh[CG][DW];
+    wait_vm<0>();  // this wave's loads of the stage (if it issued any) are in LDS
 #pragma unroll
-    for (int u = 0; u < CG; ++u) {
-      const Win g = gq[u];
-      const uint32_t boff = sbase + u * slot_bytes;
-      off[u] = g.off;
-      // Delays of this wave's trials at the channel, read before the barrier
-      // so that its wait covers these scalar loads too.
-      cint32* sr = srow + static_cast<int64_t>(min(c0 + u, nlast)) * a.ndm_pad;
+    for (int u = 0; u < CG; ++u) patch(c0 + u, ce[u], cn[u], sbase + u * slot_bytes);
+    lds_barrier_asm();
+    // the other stage's slots are free: issue the next stage
 #pragma unroll
-      for (int j = 0; j < DW; ++j) sh[u][j] = sr[j];
-      // Hand the window to LDS: a wave writes a run of 64 units when the run
-      // starts inside the window (the slot has 64 units of slack after it).
-      // (a stage's channels past the last one stay all zeros)
-      if (__builtin_expect(g.rem >= 4 * static_cast<int64_t>(g.n4) || c0 + u > nlast, 1)) {
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-          if (r * NT + 64 * wave < g.n4) put(boff, tid + r * NT, raw[u][r], false);
-      } else {  // the window reaches the last, partial group of the input
-        const int itail = static_cast<int>(g.rem >> 2);  // unit holding the tail
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-          if (r * NT + 64 * wave < g.n4) put(boff, tid + r * NT, raw[u][r], tid + r * NT == itail);
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < CG; ++u) {
-      gq[u] = window(c0 + CG + u);
-      issue(gq[u], raw[u], c0 + CG + u < nchans);
-    }
-    lds_barrier();
+    for (int u = 0; u < CG; ++u) issue(c0 + CG + u, ne[u], nn[u], (sbase ^ (CG * slot_bytes)) + u * slot_bytes);
 
-    // (channel, trial) blocks of the stage, reads D blocks ahead.  Channels
-    // past the last one read zeros and add nothing.
     uint32_t ba[NB];
     int pb[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int u = b / DW, j = b % DW;
-      const int p = sh[u][j] + off[u];
+      const int p = sh[u][j] + ce[u] + tw;
       pb[b] = p;
-      ba[b] = vlane + sbase + u * slot_bytes +
-              (kU8 ? 8u * static_cast<uint32_t>(p >> 2) : 4u * static_cast<uint32_t>(p & ~1));
+      ba[b] = vlane + (sbase + u * slot_bytes +
+                       (kPairs ? 8u * static_cast<uint32_t>(p >> 2) : 4u * static_cast<uint32_t>(p & ~1)));
     }
     v2u rb[D][NR];
 #pragma unroll
     for (int b = 0; b < D && b < NB; ++b) lds_reads<NR>(ba[b], rb[b]);
+    // scalar loads for later stages, consumed a stage from now
+#pragma unroll
+    for (int u = 0; u < CG; ++u) {
+      fe[u] = gp[2 * u];
+      fn[u] = gp[2 * u + 1];
+#pragma unroll
+      for (int j = 0; j < DW; ++j) shn[u][j] = sp[u * a.ndm_pad + j];
+    }
+    gp += 2 * CG;
+    sp += CG * a.ndm_pad;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int ahead = (NB - 1 - b) < (D - 1) ? (NB - 1 - b) : (D - 1);
@@ -771,44 +579,28 @@ __device__ __forceinline__ void tile_body(const TiledArgs& a, int dm_tile, int t
         lds_wait<NR>();
       else
         lds_wait<0>();
-      const int j = b % DW;
-      if constexpr (kU8)
-        TrialAdds<NR>::u8(acc0[j], acc1[j], rb[b % D], pb[b]);
-      else
-        TrialAdds<NR>::f32(acc0[j], rb[b % D], pb[b]);
+      // a stage past the last channel reads stale LDS and adds nothing
+      if (b < DW || c0 + b / DW < nchans) {
+        if constexpr (kPairs)
+          TrialAdds<NR>::u8(acc0[b % DW], acc1[b % DW], rb[b % D], pb[b]);
+        else
+          TrialAdds<NR>::f32(acc0[b % DW], rb[b % D], pb[b]);
+      }
       if (b + D < NB) lds_reads<NR>(ba[b + D], rb[(b + D) % D]);
     }
-
-    const int c1 = c0 + CG;  // channels done after this stage
-    if constexpr (kU8) {
-      if ((c1 & 255) == 0 || c1 >= nchans) {
+    if (((c0 + CG) % FLUSH) == 0) flush();
 #pragma unroll
-        for (int j = 0; j < DW; ++j)
+    for (int u = 0; u < CG; ++u) {
+      ce[u] = ne[u];
+      cn[u] = nn[u];
+      ne[u] = fe[u];
+      nn[u] = fn[u];
 #pragma unroll
-          for (int k = 0; k < NR; ++k) {
-            const uint32_t ex = acc0[j][2 * k], ey = acc0[j][2 * k + 1];
-            const uint32_t ox = acc1[j][2 * k], oy = acc1[j][2 * k + 1];
-            const uint32_t oxn = from_next_lane(ox);
-            tot[j][4 * k + 0] += (ex & 0xffffu) + (ox >> 16);
-            tot[j][4 * k + 1] += (ex >> 16) + (oy & 0xffffu);
-            tot[j][4 * k + 2] += (ey & 0xffffu) + (oy >> 16);
-            tot[j][4 * k + 3] += (ey >> 16) + (oxn & 0xffffu);
-            acc0[j][2 * k] = acc0[j][2 * k + 1] = 0u;
-            acc1[j][2 * k] = acc1[j][2 * k + 1] = 0u;
-          }
-      }
-    } else {
-      if ((c1 % kChanBlock) == 0 || c1 >= nchans) {
-#pragma unroll
-        for (int j = 0; j < DW; ++j)
-#pragma unroll
-          for (int k = 0; k < NA; ++k) {
-            tot[j][k] += acc0[j][k];
-            acc0[j][k] = 0.f;
-          }
-      }
+      for (int j = 0; j < DW; ++j) sh[u][j] = shn[u][j];
     }
   }
+  flush();       // the channels after the last whole flush block
+  wait_vm<0>();  // no load may still be writing LDS when the workgroup ends
 
   if (lane == 63) return;  // the halo lane owns no output
   const int64_t nsamp = a.nsamp;
@@ -816,10 +608,10 @@ __device__ __forceinline__ void tile_body(const TiledArgs& a, int dm_tile, int t
   for (int j = 0; j < DW; ++j) {
     const int d = dw0 + j;
     if (d >= a.ndm) break;
-    if constexpr (kU8) {
+    if constexpr (kPairs) {
 #pragma unroll
       for (int k = 0; k < NR; ++k) {
-        const int64_t t = t0 + tw + 4 * lane + 252 * k;
+        const int64_t t = static_cast<int64_t>(t0) + tw + 4 * lane + 252 * k;
         int32_t* o = static_cast<int32_t*>(a.out) + d * nsamp + t;
         if (t + 3 < nsamp) {
           const int4 w4 = make_int4(static_cast<int32_t>(tot[j][4 * k]), static_cast<int32_t>(tot[j][4 * k + 1]),
@@ -834,7 +626,7 @@ __device__ __forceinline__ void tile_body(const TiledArgs& a, int dm_tile, int t
     } else {
 #pragma unroll
       for (int k = 0; k < NR; ++k) {
-        const int64_t t = t0 + tw + 2 * lane + 126 * k;
+        const int64_t t = static_cast<int64_t>(t0) + tw + 2 * lane + 126 * k;
         float* o = static_cast<float*>(a.out) + d * nsamp + t;
         if (t + 1 < nsamp) {
           const float2 w2 = make_float2(tot[j][2 * k], tot[j][2 * k + 1]);
@@ -847,18 +639,94 @@ __device__ __forceinline__ void tile_body(const TiledArgs& a, int dm_tile, int t
   }
 }
 
-template <typename In, int DW, int KS, int WD, int WT, int R, int CG>
+// One tile: 8-bit input (widened to 16 bits) as pairs, float and half
+// (widened to float) as float32.
+template <typename In, int DW, int KS, int WD, int WT, int CG>
+__device__ __forceinline__ void tile_body(const TiledArgs& a, int dm_tile, int t_tile) {
+  tile_dma<sizeof(In) == 1, DW, KS, WD, WT, CG>(a, dm_tile, t_tile);
+}
+
+// Widening of 8-bit input to 16 bits and of half input to float, into a
+// buffer padded with zeros to npad samples (a multiple of 8): 8 samples per
+// thread.
+__global__ __launch_bounds__(256) void widen_u8(const uint8_t* __restrict__ in, uint16_t* __restrict__ out,
+                                                int64_t n, int64_t npad) {
+  const int64_t i = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) * 8;
+  if (i >= npad) return;
+  if (i + 8 <= n) {
+    uint2 w;
+    __builtin_memcpy(&w, in + i, 8);
+    uint4 o;
+    o.x = (w.x & 0xffu) | ((w.x & 0xff00u) << 8);
+    o.y = ((w.x >> 16) & 0xffu) | ((w.x >> 8) & 0xff0000u);
+    o.z = (w.y & 0xffu) | ((w.y & 0xff00u) << 8);
+    o.w = ((w.y >> 16) & 0xffu) | ((w.y >> 8) & 0xff0000u);
+    *reinterpret_cast<uint4*>(out + i) = o;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) out[i + k] = i + k < n ? in[i + k] : 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void widen_f16(const __half* __restrict__ in, float* __restrict__ out, int64_t n,
+                                                 int64_t npad) {
+  const int64_t i = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) * 8;
+  if (i >= npad) return;
+  if (i + 8 <= n) {
+    uint4 w;
+    __builtin_memcpy(&w, in + i, 16);
+    float4 lo = make_float4(h2f(w.x & 0xffffu), h2f(w.x >> 16), h2f(w.y & 0xffffu), h2f(w.y >> 16));
+    float4 hi = make_float4(h2f(w.z & 0xffffu), h2f(w.z >> 16), h2f(w.w & 0xffffu), h2f(w.w >> 16));
+    reinterpret_cast<float4*>(out + i)[0] = lo;
+    reinterpret_cast<float4*>(out + i)[1] = hi;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) out[i + k] = i + k < n ? __half2float(in[i + k]) : 0.f;
+  }
+}
+
+
+template <typename In, int DW, int KS, int WD, int WT, int CG>
 __global__ __launch_bounds__(64 * WD * WT) void dedisp_tiled(const TiledArgs a) {
   int dm_tile, t_tile;
   if (!tile_of(a, dm_tile, t_tile)) return;  // padding block of the last group
-  tile_body<In, DW, KS, WD, WT, R, CG>(a, dm_tile, t_tile);
+  tile_body<In, DW, KS, WD, WT, CG>(a, dm_tile, t_tile);
+}
+
+// Widening of the inputs of a batch: blockIdx.y selects the job, the blocks
+// of a job stride over its samples, 8 per thread.
+__global__ __launch_bounds__(256) void widen_job_kernel(const WidenJob* __restrict__ jobs) {
+  const WidenJob j = jobs[blockIdx.y];
+  for (int64_t i = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) * 8; i < j.npad;
+       i += static_cast<int64_t>(gridDim.x) * 256 * 8) {
+    if (j.dtype == DEDISP_U8) {
+      const uint8_t* in = static_cast<const uint8_t*>(j.in);
+      uint16_t* out = static_cast<uint16_t*>(j.ws);
+      if (i + 8 <= j.n) {
+        uint2 w;
+        __builtin_memcpy(&w, in + i, 8);
+        uint4 o;
+        o.x = (w.x & 0xffu) | ((w.x & 0xff00u) << 8);
+        o.y = ((w.x >> 16) & 0xffu) | ((w.x >> 8) & 0xff0000u);
+        o.z = (w.y & 0xffu) | ((w.y & 0xff00u) << 8);
+        o.w = ((w.y >> 16) & 0xffu) | ((w.y >> 8) & 0xff0000u);
+        *reinterpret_cast<uint4*>(out + i) = o;
+      } else {
+        for (int k = 0; k < 8; ++k) out[i + k] = i + k < j.n ? in[i + k] : 0;
+      }
+    } else {
+      const __half* in = static_cast<const __half*>(j.in);
+      float* out = static_cast<float*>(j.ws);
+      for (int k = 0; k < 8; ++k) out[i + k] = i + k < j.n ? __half2float(in[i + k]) : 0.f;
+    }
+  }
 }
 
 // Persistent batch kernel: resident workgroups pull (beam, trial tile, time
 // tile) items from one atomic counter until none are left.  Items are
 // numbered beam by beam, beams in order of decreasing cost per item (longest
 // items first), and inside a beam in the same groups as a single launch.
-template <int DW, int KS, int WD, int WT, int R, int CG>
+template <int DW, int KS, int WD, int WT, int CG>
 __global__ __launch_bounds__(64 * WD * WT) void dedisp_batch_persistent(const BatchArgs b) {
   __shared__ long long item_s;
   for (;;) {
@@ -885,11 +753,11 @@ __global__ __launch_bounds__(64 * WD * WT) void dedisp_batch_persistent(const Ba
     if (dm_tile < a.n_dm_tiles && t_tile < a.n_t_tiles) {
       const int dt = ((cint32*)(b.dtype))[beam];
       if (dt == DEDISP_F32)
-        tile_body<float, DW, KS, WD, WT, R, CG>(a, dm_tile, t_tile);
+        tile_body<float, DW, KS, WD, WT, CG>(a, dm_tile, t_tile);
       else if (dt == DEDISP_U8)
-        tile_body<uint8_t, DW, KS, WD, WT, R, CG>(a, dm_tile, t_tile);
+        tile_body<uint8_t, DW, KS, WD, WT, CG>(a, dm_tile, t_tile);
       else
-        tile_body<__half, DW, KS, WD, WT, R, CG>(a, dm_tile, t_tile);
+        tile_body<__half, DW, KS, WD, WT, CG>(a, dm_tile, t_tile);
     }
     lds_barrier();  // every wave is done with this item's LDS before the next
   }
@@ -901,29 +769,31 @@ __global__ void reset_counter(unsigned long long* c) { *c = 0ull; }
 
 struct Variant {
   TileShape shape;
-  int r;              // staging 4-sample units per thread and channel
   int cg;             // channels per stage
   const void* fn[3];  // by dtype: U8, F16, F32
   const void* batch;  // persistent batch kernel
 };
 
-#define DEDISP_VARIANT(DW, KS, WD, WT, R, CG)                                                       \
+#define DEDISP_VARIANT(DW, KS, WD, WT, CG)                                                          \
   Variant {                                                                                        \
-    TileShape{DW, KS, WD, WT}, R, CG,                                                              \
-        {reinterpret_cast<const void*>(&dedisp_tiled<uint8_t, DW, KS, WD, WT, R, CG>),              \
-         reinterpret_cast<const void*>(&dedisp_tiled<__half, DW, KS, WD, WT, R, CG>),               \
-         reinterpret_cast<const void*>(&dedisp_tiled<float, DW, KS, WD, WT, R, CG>)},               \
-        reinterpret_cast<const void*>(&dedisp_batch_persistent<DW, KS, WD, WT, R, CG>)              \
+    TileShape{DW, KS, WD, WT}, CG,                                                                 \
+        {reinterpret_cast<const void*>(&dedisp_tiled<uint8_t, DW, KS, WD, WT, CG>),                 \
+         reinterpret_cast<const void*>(&dedisp_tiled<__half, DW, KS, WD, WT, CG>),                  \
+         reinterpret_cast<const void*>(&dedisp_tiled<float, DW, KS, WD, WT, CG>)},                  \
+        reinterpret_cast<const void*>(&dedisp_batch_persistent<DW, KS, WD, WT, CG>)                 \
   }
 
 const Variant kVariants[] = {
-    DEDISP_VARIANT(4, 8, 4, 2, 4, 2),  // 16 trials x 2016 samples, 512 threads, 2 channels per stage
-    DEDISP_VARIANT(4, 8, 4, 2, 4, 1),  // 16 x 2016, 512 threads, 1 channel per stage
-    DEDISP_VARIANT(4, 8, 2, 4, 4, 2),  // 8 x 4032, 512 threads
-    DEDISP_VARIANT(4, 8, 4, 2, 4, 4),  // 16 x 2016, 512 threads, 4 channels per stage
-    DEDISP_VARIANT(2, 8, 8, 2, 2, 2),  // 16 x 2016, 1024 threads
-    DEDISP_VARIANT(8, 4, 2, 4, 4, 2),  // 16 x 2016, 512 threads
-    DEDISP_VARIANT(4, 8, 8, 1, 8, 2),  // 32 x 1008, 512 threads
+    DEDISP_VARIANT(2, 8, 4, 2, 2),  // 8 trials x 2016 samples, 512 threads (several workgroups per CU)
+    DEDISP_VARIANT(2, 8, 8, 2, 2),  // 16 x 2016, 1024 threads
+    DEDISP_VARIANT(4, 8, 4, 2, 2),  // 16 x 2016, 512 threads
+    DEDISP_VARIANT(2, 8, 4, 4, 2),  // 8 x 4032, 1024 threads
+    DEDISP_VARIANT(2, 8, 4, 2, 4),  // 8 x 2016, 512 threads, 4 channels per stage
+    DEDISP_VARIANT(2, 8, 8, 2, 4),  // 16 x 2016, 1024 threads, 4 channels per stage
+    DEDISP_VARIANT(4, 8, 4, 2, 4),  // 16 x 2016, 512 threads, 4 channels per stage
+    DEDISP_VARIANT(2, 8, 4, 2, 1),  // 8 x 2016, 512 threads, 1 channel per stage
+    DEDISP_VARIANT(4, 8, 8, 1, 2),  // 32 x 1008, 512 threads
+    DEDISP_VARIANT(2, 4, 8, 2, 2),  // 16 x 1008, 1024 threads
 };
 constexpr int kNumTiled = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -931,29 +801,28 @@ constexpr size_t kMaxLds = 160 * 1024;
 
 // 4-sample units per LDS slot (one channel's window) a tiled variant needs
 // for this plan, or 0 if the plan's delay spread is too wide for the
-// variant's LDS or staging registers.  A window covers the tile's samples,
-// the delay spread of its trials, up to 3 samples of alignment in front and
-// the neighbour words read past the last sample; a slot has 64 units of
-// slack for the last wave-wide run of writes.  Two stages of `cg` slots are
+// variant's LDS.  A window covers the tile's samples, the delay spread of its
+// trials, the alignment of its start (to 4 samples for float staging, 8 for
+// 16-bit pairs) and the neighbour words read past the last sample; a slot has
+// one load (1 KB) of slack for the last run.  Two stages of `cg` slots are
 // live.
 int lds_units(dedisp_plan p, const Variant& v) {
   const std::vector<int2>& w = host_windows(p, v.shape.dms());
   int spread = 0;
   for (const int2& x : w) spread = std::max(spread, x.y - x.x);
-  const int64_t n4 = (3 + static_cast<int64_t>(spread) + v.shape.samples() + 7) / 4;
-  if (n4 > static_cast<int64_t>(v.r) * v.shape.threads()) return 0;
-  // float input: a slot holds one 64-unit run per wave and load (R*NT units)
-  const int64_t units = p->dtype == DEDISP_F32 ? static_cast<int64_t>(v.r) * v.shape.threads() : n4 + 64;
   const int64_t unit = p->dtype == DEDISP_U8 ? 8 : 16;
+  const int64_t align = p->dtype == DEDISP_U8 ? 8 : 4;
+  const int64_t n4 = (align - 1 + static_cast<int64_t>(spread) + v.shape.samples() + 7) / 4;
+  const int64_t units = n4 + 1024 / unit;
   if (2 * v.cg * units * unit > static_cast<int64_t>(kMaxLds) - 256) return 0;  // 256 B for static LDS
   return static_cast<int>(units);
 }
 
-// The tiled float kernel addresses its input with 32-bit byte offsets,
-// including the rows it reads ahead past the last channel.
-bool f32_offsets_fit(dedisp_plan p, int64_t nsamp) {
+// The tiled kernels address their input with 32-bit byte offsets, including
+// the rows they read ahead past the last channel.
+bool offsets_fit(dedisp_plan p, int64_t nsamp) {
   const int64_t pitch = nsamp + p->max_shift;
-  return (static_cast<int64_t>(p->nchans) + 16) * pitch * 4 + (static_cast<int64_t>(1) << 24) <
+  return (static_cast<int64_t>(p->nchans) + 16) * pitch * staged_size(p->dtype) + (static_cast<int64_t>(1) << 24) <
          (static_cast<int64_t>(1) << 32);
 }
 
@@ -970,13 +839,13 @@ bool variant_fits(dedisp_plan p, int v) {
 }
 
 int default_variant(dedisp_plan p) {
-  static const int order[] = {1, 2, 3, 4, 5, 6, 7};
+  static const int order[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 10};
   for (int v : order)
     if (v <= kNumTiled && variant_fits(p, v)) return v;
   return 0;
 }
 
-int launch(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, hipStream_t s) {
+int launch(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, hipStream_t s, void* ws_given) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
@@ -987,7 +856,7 @@ int launch(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, hipSt
   const int64_t total = pitch * p->nchans;
   // the tiled float kernel addresses its input with 32-bit byte offsets;
   // larger float inputs take the direct kernel
-  if (v > 0 && p->dtype == DEDISP_F32 && !f32_offsets_fit(p, nsamp)) v = 0;
+  if (v > 0 && !offsets_fit(p, nsamp)) v = 0;
   if (v == 0) {
     const int64_t tblocks = (nsamp + 255) / 256;
     const int64_t nblocks = tblocks * p->ndm;
@@ -1010,20 +879,62 @@ int launch(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, hipSt
     }
     return DEDISP_HIP_STATUS(hipGetLastError());
   }
+  // 8-bit and half input are widened into a stream-ordered workspace first
+  void* ws = nullptr;
+  bool own_ws = false;
+  if (p->dtype != DEDISP_F32) {
+    ws = ws_given;
+    if (ws == nullptr) {
+      const int64_t npad = widened_samples(total);
+      e = hipMallocAsync(&ws, static_cast<size_t>(npad) * staged_size(p->dtype), s);
+      if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
+      own_ws = true;
+    }
+    st = widen(p->dtype, in, ws, total, s);
+    if (st != DEDISP_OK) {
+      if (own_ws) (void)hipFreeAsync(ws, s);
+      return st;
+    }
+  }
   TiledArgs a;
   size_t lds = 0;
   int64_t nblocks = 0;
   int threads = 0;
-  st = tiled_args(p, v, in, out, nsamp, &a, &lds, &nblocks, &threads);
-  if (st != DEDISP_OK) return st;
+  st = tiled_args(p, v, ws ? ws : in, out, nsamp, &a, &lds, &nblocks, &threads);
   const void* fn = kVariants[v - 1].fn[p->dtype];
-  if (lds > 64 * 1024) {
-    st = allow_large_lds(fn);
-    if (st != DEDISP_OK) return st;
+  if (st == DEDISP_OK && lds > 64 * 1024) st = allow_large_lds(fn);
+  if (st == DEDISP_OK) {
+    void* args[] = {&a};
+    st = DEDISP_HIP_STATUS(hipLaunchKernel(fn, dim3(static_cast<unsigned>(nblocks)), dim3(threads), args, lds, s));
   }
-  void* args[] = {&a};
-  e = hipLaunchKernel(fn, dim3(static_cast<unsigned>(nblocks)), dim3(threads), args, lds, s);
-  return DEDISP_HIP_STATUS(e);
+  if (own_ws) {
+    const int st2 = DEDISP_HIP_STATUS(hipFreeAsync(ws, s));
+    if (st == DEDISP_OK) st = st2;
+  }
+  return st;
+}
+
+int widen_jobs(const WidenJob* jobs, int njobs, hipStream_t s) {
+  if (njobs <= 0) return DEDISP_OK;
+  hipLaunchKernelGGL(widen_job_kernel, dim3(1024, static_cast<unsigned>(njobs)), dim3(256), 0, s, jobs);
+  return DEDISP_HIP_STATUS(hipGetLastError());
+}
+
+int64_t widened_samples(int64_t total) { return (total + 7) / 8 * 8; }
+
+int widen(int dtype, const void* in, void* ws, int64_t total, hipStream_t s) {
+  const int64_t npad = widened_samples(total);
+  const int64_t blocks = (npad / 8 + 255) / 256;
+  if (blocks > INT32_MAX) return DEDISP_ERR_INVALID_ARG;
+  if (dtype == DEDISP_U8)
+    hipLaunchKernelGGL(widen_u8, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                       static_cast<const uint8_t*>(in), static_cast<uint16_t*>(ws), total, npad);
+  else if (dtype == DEDISP_F16)
+    hipLaunchKernelGGL(widen_f16, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                       static_cast<const __half*>(in), static_cast<float*>(ws), total, npad);
+  else
+    return DEDISP_ERR_INVALID_ARG;
+  return DEDISP_HIP_STATUS(hipGetLastError());
 }
 
 int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, TiledArgs* ap, size_t* lds_out,
@@ -1046,19 +957,25 @@ int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, T
   TiledArgs& a = *ap;
   a.in = in;
   a.pitch = pitch;
-  a.total4 = total & ~static_cast<int64_t>(3);
-  a.ntail = static_cast<int>(total - a.total4);
+  if (p->dtype == DEDISP_F32) {
+    a.total4 = total & ~static_cast<int64_t>(3);
+    a.ntail = static_cast<int>(total - a.total4);
+  } else {  // widened input, padded with zeros to whole groups of 8
+    a.total4 = widened_samples(total);
+    a.ntail = 0;
+  }
   a.max_shift = p->max_shift;
   a.out = out;
   a.nsamp = nsamp;
   a.shift = dt->shift;
   a.win = reinterpret_cast<const int32_t*>(win);
   a.geo = nullptr;
-  if (p->dtype == DEDISP_F32) {
-    // the float kernel addresses the input with 32-bit byte offsets
-    if (!f32_offsets_fit(p, nsamp)) return DEDISP_ERR_INVALID_ARG;
+  {
+    // the tiled kernels address the input with 32-bit byte offsets
+    if (!offsets_fit(p, nsamp)) return DEDISP_ERR_INVALID_ARG;
     const int2* geo = nullptr;
-    st = device_geo(p, dev, var.shape.dms(), var.shape.samples(), static_cast<int>(pitch & 3), &geo);
+    const int align = p->dtype == DEDISP_U8 ? 8 : 4;
+    st = device_geo(p, dev, var.shape.dms(), var.shape.samples(), align, static_cast<int>(pitch % align), &geo);
     if (st != DEDISP_OK) return st;
     a.geo = reinterpret_cast<const int32_t*>(geo);
   }
@@ -1113,10 +1030,11 @@ int prepare(dedisp_plan p, int v, int64_t nsamp) {
   const int2* w = nullptr;
   st = device_windows(p, dev, variant_shape(v).dms(), &w);
   if (st != DEDISP_OK) return st;
-  if (p->dtype == DEDISP_F32) {
+  {
     const int2* g = nullptr;
-    st = device_geo(p, dev, variant_shape(v).dms(), variant_shape(v).samples(),
-                    static_cast<int>((nsamp + p->max_shift) & 3), &g);
+    const int align = p->dtype == DEDISP_U8 ? 8 : 4;
+    st = device_geo(p, dev, variant_shape(v).dms(), variant_shape(v).samples(), align,
+                    static_cast<int>((nsamp + p->max_shift) % align), &g);
     if (st != DEDISP_OK) return st;
   }
   return allow_large_lds(kVariants[v - 1].fn[p->dtype]);

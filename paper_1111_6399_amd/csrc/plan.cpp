@@ -148,10 +148,10 @@ int device_tables(dedisp_plan p, int device, DeviceTables** out) {
   DeviceTables& t = p->dev[device];
   if (t.shift == nullptr) {
     // Rows padded to a multiple of 64 trials, pad entries repeat the last trial
-    // so that every padded read stays inside the window of its tile.  Two
-    // rows of zeros follow the last channel: kernels read the delays of the
-    // next channel ahead without a bounds check.
-    std::vector<int32_t> padded(static_cast<size_t>(p->nchans + 2) * p->ndm_pad, 0);
+    // so that every padded read stays inside the window of its tile.  Rows
+    // of zeros follow the last channel: kernels read the delays of channels
+    // ahead without a bounds check.
+    std::vector<int32_t> padded(static_cast<size_t>(p->nchans + kShiftPadRows) * p->ndm_pad, 0);
     for (int c = 0; c < p->nchans; ++c) {
       const int32_t* src = p->shift.data() + static_cast<size_t>(c) * p->ndm;
       int32_t* dst = padded.data() + static_cast<size_t>(c) * p->ndm_pad;
@@ -192,25 +192,26 @@ int device_windows(dedisp_plan p, int device, int dms_per_tile, const int2** out
   return DEDISP_OK;
 }
 
-int device_geo(dedisp_plan p, int device, int dms_per_tile, int samples, int pitch_mod4, const int2** out) {
+int device_geo(dedisp_plan p, int device, int dms_per_tile, int samples, int align, int pitch_mod, const int2** out) {
   const std::vector<int2>& hw = host_windows(p, dms_per_tile);
-  const int64_t key = (static_cast<int64_t>(dms_per_tile) << 40) | (static_cast<int64_t>(samples) << 8) | pitch_mod4;
+  const int64_t key = (static_cast<int64_t>(dms_per_tile) << 40) | (static_cast<int64_t>(samples) << 12) |
+                      (static_cast<int64_t>(align) << 4) | pitch_mod;
   std::lock_guard<std::mutex> g(p->mu);
   DeviceTables& t = p->dev[device];
   auto it = t.geo.find(key);
   if (it == t.geo.end()) {
     const int ntiles = static_cast<int>(hw.size() / p->nchans);
-    std::vector<int2> geo(hw.size());
+    const int stride = p->nchans + kGeoPad;
+    // each tile's row ends with kGeoPad zero entries: kernels read the
+    // windows of channels ahead without a bounds check
+    std::vector<int2> geo(static_cast<size_t>(ntiles) * stride, make_int2(0, 0));
     for (int tile = 0; tile < ntiles; ++tile)
       for (int c = 0; c < p->nchans; ++c) {
         const int2 w = hw[static_cast<size_t>(tile) * p->nchans + c];
-        // alignment of the window start c*pitch + t0 + lo (t0 is a multiple of 4)
-        const int mis = static_cast<int>((static_cast<int64_t>(c) * pitch_mod4 + w.x) & 3);
-        geo[static_cast<size_t>(tile) * p->nchans + c] = make_int2(mis - w.x, (mis + (w.y - w.x) + samples + 7) >> 2);
+        // alignment of the window start c*pitch + t0 + lo (t0 is a multiple of align)
+        const int mis = static_cast<int>((static_cast<int64_t>(c) * pitch_mod + w.x) % align);
+        geo[static_cast<size_t>(tile) * stride + c] = make_int2(mis - w.x, (mis + (w.y - w.x) + samples + 7) >> 2);
       }
-    // entries past the last (tile, channel) are zero: kernels read the window
-    // of channels ahead without a bounds check
-    geo.resize(geo.size() + kGeoPad, make_int2(0, 0));
     int2* dptr = nullptr;
     hipError_t e = hipMalloc(&dptr, geo.size() * sizeof(int2));
     if (e != hipSuccess) return hip_status(e);
