@@ -29,6 +29,31 @@ UNIT = "DM·chan·samples/s"
 # 157.3 TFLOP/s fp32 vector peak counted as one add per FMA slot.
 ALU_PEAK_TADDS = 256 * 128 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
+# LDS read rate of the accumulation's access pattern (64-bit reads, 512
+# contiguous bytes per wave read), measured on MI355X: about 205 bytes per
+# clock per CU.
+LDS_READ_TBS = 205 * 256 * 2.4e9 / 1e12
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1111_6399_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_sha() -> str:
+    import hashlib
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+
+
+def measured_traffic(workload_name: str, variant: int):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary (scaled by a plain copy), or None when the
+    kernel source or variant differs from the one the counters were taken on."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE)).get(workload_name)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("kernel_sha256") != kernel_sha() or rec.get("variant") != variant:
+        return None
+    return {"bytes": rec["fetch_bytes"] + rec["write_bytes"], "fetch_bytes": rec["fetch_bytes"],
+            "write_bytes": rec["write_bytes"], "source": rec.get("source")}
 
 
 def log(msg: str) -> None:
@@ -370,6 +395,21 @@ def run_served(args) -> dict:
     }
 
 
+def roofline(w, adds, alg_bytes, kernel_ms, variant) -> dict:
+    """Achieved add rate of the timed launch (HIP events on its stream) against
+    the ALU add peak, with the LDS-read ceiling the accumulation also meets
+    (4 bytes per float add, 2 per 8-bit add) and the HBM traffic."""
+    achieved = adds / (kernel_ms * 1e-3) / 1e12
+    lds_bytes_per_add = (2.0 if w.dtype == "u8" else 4.0) * 64.0 / 63.0
+    lds_tbs = achieved * lds_bytes_per_add
+    tr = measured_traffic(w.name, variant)
+    return {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TADDS, "unit": "Tadd/s",
+            "frac": achieved / ALU_PEAK_TADDS, "traffic": None if tr is None else tr["bytes"],
+            "traffic_detail": tr, "kernel_ms": kernel_ms, "alg_bytes": alg_bytes,
+            "hbm_alg_GBps": alg_bytes / (kernel_ms * 1e-3) / 1e9,
+            "lds_read_TBps": lds_tbs, "lds_read_peak_TBps": LDS_READ_TBS, "lds_frac": lds_tbs / LDS_READ_TBS}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -449,7 +489,6 @@ def main() -> int:
     adds = float(w.ndm) * b.nchans * w.nsamp
     value = adds / (ms_per_step * 1e-3)
     rtf = w.nsamp * b.tsamp / (ms_per_step * 1e-3)
-    achieved = adds / (kernel_ms * 1e-3) / 1e12
     esize = x.itemsize
     alg_bytes = (b.nchans * (w.nsamp + plan.max_shift) * esize + w.ndm * w.nsamp * 4
                  + b.nchans * w.ndm * 4)
@@ -483,9 +522,7 @@ def main() -> int:
                    "f_top_mhz": b.f_top, "df_mhz": b.df, "tsamp_s": b.tsamp, "max_shift": plan.max_shift,
                    "variant": plan.variant},
         "rtf": rtf, "pct_realtime": 100.0 / rtf, "parity_spot_check": ok,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TADDS, "unit": "Tadd/s",
-                     "frac": achieved / ALU_PEAK_TADDS, "traffic": None,
-                     "kernel_ms": kernel_ms, "hbm_alg_GBps": alg_bytes / (kernel_ms * 1e-3) / 1e9},
+        "roofline": roofline(w, adds, alg_bytes, kernel_ms, plan.variant),
     }
     if not args.no_cpu_baseline:
         log("timing the oracle on the host ...")
