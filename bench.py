@@ -285,7 +285,7 @@ def run_served(args) -> dict:
         the warm-up, the completion span and the largest backlog."""
         outs = [torch.empty((ndm, B), dtype=torch.int32, device=dev) for _ in range(nslots)]
         free = list(range(nslots))
-        backlog, running, lat = [], [], []
+        backlog, running, lat, sub_s = [], [], [], []
         t_start = time.perf_counter() + 0.05
         i, max_backlog, overload = 0, 0, False
         first_done = last_done = None
@@ -316,7 +316,9 @@ def run_served(args) -> dict:
             while backlog and free:
                 arr = backlog[0]
                 slot = free[-1]
+                t0 = time.perf_counter()
                 h = submit(arr[1], pool[(arr[1] * 7919 + arr[2]) % len(pool)], outs[slot])
+                sub_s.append(time.perf_counter() - t0)
                 if h is None:
                     break
                 backlog.pop(0)
@@ -326,17 +328,20 @@ def run_served(args) -> dict:
             if not progressed:
                 time.sleep(0.0002)
         del outs
-        return np.array(lat), (first_done, last_done), (max_backlog, overload)
+        return np.array(lat), (first_done, last_done), (max_backlog, overload, np.array(sub_s))
 
     def summary(lat, span, backlog, label):
         n = lat.size
         p50, p99 = (float(np.percentile(lat, 50)), float(np.percentile(lat, 99))) if n else (None, None)
         thr = (n - 1) * work / max(span[1] - span[0], 1e-9) if n > 1 else None
-        log("%s: %d blocks after warm-up, p50 %.1f ms, p99 %.1f ms, %.3g adds/s, max backlog %d%s"
-            % (label, n, 1e3 * (p50 or 0), 1e3 * (p99 or 0), thr or 0, backlog[0],
-               " (OVERLOADED: arrivals stopped)" if backlog[1] else ""))
+        sub = backlog[2]
+        sub_mean, sub_max = (float(sub.mean()), float(sub.max())) if sub.size else (None, None)
+        log("%s: %d blocks after warm-up, p50 %.1f ms, p99 %.1f ms, %.3g adds/s, max backlog %d, "
+            "submit call %.2f ms mean %.2f ms max%s"
+            % (label, n, 1e3 * (p50 or 0), 1e3 * (p99 or 0), thr or 0, backlog[0], 1e3 * (sub_mean or 0),
+               1e3 * (sub_max or 0), " (OVERLOADED: arrivals stopped)" if backlog[1] else ""))
         return {"blocks": n, "p50_s": p50, "p99_s": p99, "value": thr, "max_backlog": backlog[0],
-                "overloaded": backlog[1]}
+                "overloaded": backlog[1], "submit_mean_s": sub_mean, "submit_max_s": sub_max}
 
     server = dd.dedisp_server_create(int(args.budget_gb * (1 << 30)), args.inflight)
     try:
@@ -423,7 +428,7 @@ def main() -> int:
     ap.add_argument("--duration", type=float, default=60.0, help="served: measured seconds after the warm-up")
     ap.add_argument("--warmup-s", type=float, default=10.0, help="served: warm-up seconds")
     ap.add_argument("--inflight", type=int, default=8, help="served: requests in flight")
-    ap.add_argument("--budget-gb", type=float, default=64.0, help="served: device memory budget")
+    ap.add_argument("--budget-gb", type=float, default=128.0, help="served: device memory budget")
     ap.add_argument("--pool", type=int, default=4, help="served: distinct pinned blocks cycled through")
     ap.add_argument("--max-backlog", type=int, default=256, help="served: backlog that counts as overload")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -199,8 +199,11 @@ int dedisp_batch_destroy(dedisp_batch batch);
 int dedisp_server_create(size_t hbm_budget_bytes, int max_inflight, dedisp_server *out_server);
 
 /* Register a beam: plan (not owned; must outlive the server) and block length
- * B >= 1.  Allocates the beam's device history (2 x nchans x (max_shift + B)
- * samples) against the budget: DEDISP_ERR_AGAIN if it does not fit. */
+ * B >= 1.  Allocates the beam's device buffers against the budget: two windows
+ * of nchans x (max_shift + B) samples in the form the kernels read (8-bit
+ * samples as 16-bit, half as float) and one raw block of nchans x B samples.
+ * DEDISP_ERR_AGAIN if they do not fit.  A request is charged its ndm x B
+ * outputs while it runs. */
 int dedisp_server_add_beam(dedisp_server server, dedisp_plan plan, int64_t block_nsamp, int *beam_id);
 
 /*

@@ -130,9 +130,20 @@ bool variant_fits(dedisp_plan p, int v);
 int default_variant(dedisp_plan p);
 
 // Launch one plan's kernel over the whole problem.  8-bit and half input is
-// widened into `ws` (widened_samples(total) * staged_size bytes) when given,
-// else into a stream-ordered allocation.
+// widened into `ws` (staged_bytes(p, nsamp) bytes) when given, else into a
+// stream-ordered allocation.
 int launch(dedisp_plan p, int variant, const void* in, void* out, int64_t nsamp, hipStream_t s, void* ws = nullptr);
+// The same over input already in staged form ([nchans][nsamp + max_shift]
+// samples, 8-bit widened to 16 bits and half to float, padded with zeros to
+// widened_samples(total)).
+int launch_staged(dedisp_plan p, int variant, const void* staged, void* out, int64_t nsamp, hipStream_t s);
+// Bytes of the staged form of a plan's input for nsamp output samples.
+size_t staged_bytes(dedisp_plan p, int64_t nsamp);
+// Assemble a streaming window in staged form: per channel, `tail` samples
+// from the end of the previous window `prev` (or zeros) followed by the raw
+// block [nchans][block] widened; dst holds [nchans][tail + block].
+int assemble(int dtype, const void* prev, const void* blk, void* dst, int64_t tail, int64_t block, int nchans,
+             bool zero_tail, hipStream_t s);
 
 // 8-bit and half input are widened (to 16 bits and to float) before a tiled
 // launch, into a buffer of widened_samples(total) samples padded with zeros.
@@ -153,8 +164,6 @@ int allow_large_lds(const void* fn);
 // Persistent batch kernel of variant v >= 1, and the counter reset kernel.
 const void* batch_kernel(int v);
 const void* reset_kernel();
-// Work-item cost of a tiled variant for a plan (channels x trials x samples
-// per item, for ordering items longest first).
 
 
 // True when the environment variable DEDISP_TRACE is set: failing HIP calls

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void dedisp_direct(const In* __restrict__ in, 
   const int64_t t = (bid % tblocks) * 256 + threadIdx.x;
   if (t >= nsamp) return;
   const int32_t* sh = shift + d;
-  if constexpr (sizeof(In) == 1) {
+  if constexpr (std::is_integral<In>::value) {  // 8-bit samples, or 8-bit samples staged as 16-bit
     int32_t acc = 0;
     for (int c = 0; c < nchans; ++c)
       acc += static_cast<int32_t>(in[c * pitch + t + sh[static_cast<int64_t>(c) * ndm_pad]]);
@@ -686,6 +686,38 @@ __global__ __launch_bounds__(256) void widen_f16(const __half* __restrict__ in, 
 }
 
 
+// Staged form of a sample: 8-bit samples widen to 16 bits, half to float.
+__device__ __forceinline__ uint16_t stage_of(uint8_t x) { return x; }
+__device__ __forceinline__ float stage_of(__half x) { return __half2float(x); }
+__device__ __forceinline__ float stage_of(float x) { return x; }
+
+// Assembly of one streaming window [nchans][tail + block] in staged form:
+// the first `tail` samples of each channel row are the last `tail` of the
+// previous window (already staged), or zeros, and the rest is the new block
+// ([nchans][block], raw) widened.  Rows are strided over blockIdx.y, the
+// samples of a row over blockIdx.x and the lanes, one sample per lane, so
+// every wave reads and writes contiguous runs.
+template <typename In, typename St>
+__global__ __launch_bounds__(256) void assemble_window(const St* __restrict__ prev, const In* __restrict__ blk,
+                                                       St* __restrict__ dst, int64_t tail, int64_t block,
+                                                       int nchans, int zero_tail) {
+  const int64_t pitch = tail + block;
+  for (int c = blockIdx.y; c < nchans; c += gridDim.y) {
+    St* d = dst + c * pitch;
+    const St* h = prev + c * pitch + block;
+    const In* b = blk + c * block;
+    for (int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; j < pitch;
+         j += static_cast<int64_t>(gridDim.x) * 256) {
+      St v;
+      if (j < tail)
+        v = zero_tail ? St(0) : h[j];
+      else
+        v = stage_of(b[j - tail]);
+      d[j] = v;
+    }
+  }
+}
+
 template <typename In, int DW, int KS, int WD, int WT, int CG>
 __global__ __launch_bounds__(64 * WD * WT) void dedisp_tiled(const TiledArgs a) {
   int dm_tile, t_tile;
@@ -845,6 +877,57 @@ int default_variant(dedisp_plan p) {
   return 0;
 }
 
+namespace {
+
+// The direct kernel over input of sample type In (raw or staged).
+template <typename In>
+int launch_direct(dedisp_plan p, const DeviceTables* dt, const void* in, void* out, int64_t nsamp, hipStream_t s) {
+  const int64_t pitch = nsamp + p->max_shift;
+  const int64_t tblocks = (nsamp + 255) / 256;
+  const int64_t nblocks = tblocks * p->ndm;
+  if (nblocks > INT32_MAX) return DEDISP_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(dedisp_direct<In>, dim3(static_cast<unsigned>(nblocks)), dim3(256), 0, s,
+                     static_cast<const In*>(in), pitch, out, nsamp, dt->shift, p->ndm_pad, p->nchans, tblocks);
+  return DEDISP_HIP_STATUS(hipGetLastError());
+}
+
+// A tiled variant over staged input (float input as given, 8-bit and half
+// input widened).
+int launch_tiled(dedisp_plan p, int v, const void* staged, void* out, int64_t nsamp, hipStream_t s) {
+  TiledArgs a;
+  size_t lds = 0;
+  int64_t nblocks = 0;
+  int threads = 0;
+  int st = tiled_args(p, v, staged, out, nsamp, &a, &lds, &nblocks, &threads);
+  const void* fn = kVariants[v - 1].fn[p->dtype];
+  if (st == DEDISP_OK && lds > 64 * 1024) st = allow_large_lds(fn);
+  if (st == DEDISP_OK) {
+    void* args[] = {&a};
+    st = DEDISP_HIP_STATUS(hipLaunchKernel(fn, dim3(static_cast<unsigned>(nblocks)), dim3(threads), args, lds, s));
+  }
+  return st;
+}
+
+// Stream-ordered workspaces come from the device's default memory pool; by
+// default the pool hands memory back to the driver at every synchronisation,
+// so each call would map its workspace anew.  Keep it instead (once per
+// device).
+int keep_pool_memory(int dev) {
+  static std::mutex mu;
+  static std::map<int, bool> done;
+  std::lock_guard<std::mutex> g(mu);
+  if (done.count(dev)) return DEDISP_OK;
+  hipMemPool_t pool = nullptr;
+  hipError_t e = hipDeviceGetDefaultMemPool(&pool, dev);
+  uint64_t keep = UINT64_MAX;
+  if (e == hipSuccess) e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
+  done[dev] = true;
+  return DEDISP_OK;
+}
+
+}  // namespace
+
 int launch(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, hipStream_t s, void* ws_given) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -852,66 +935,83 @@ int launch(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, hipSt
   DeviceTables* dt = nullptr;
   int st = device_tables(p, dev, &dt);
   if (st != DEDISP_OK) return st;
-  const int64_t pitch = nsamp + p->max_shift;
-  const int64_t total = pitch * p->nchans;
-  // the tiled float kernel addresses its input with 32-bit byte offsets;
-  // larger float inputs take the direct kernel
+  const int64_t total = (nsamp + p->max_shift) * p->nchans;
+  // the tiled kernels address their input with 32-bit byte offsets; larger
+  // inputs take the direct kernel
   if (v > 0 && !offsets_fit(p, nsamp)) v = 0;
   if (v == 0) {
-    const int64_t tblocks = (nsamp + 255) / 256;
-    const int64_t nblocks = tblocks * p->ndm;
-    if (nblocks > INT32_MAX) return DEDISP_ERR_INVALID_ARG;
     switch (p->dtype) {
-      case DEDISP_U8:
-        hipLaunchKernelGGL(dedisp_direct<uint8_t>, dim3(static_cast<unsigned>(nblocks)), dim3(256), 0, s,
-                           static_cast<const uint8_t*>(in), pitch, out, nsamp, dt->shift, p->ndm_pad, p->nchans,
-                           tblocks);
-        break;
-      case DEDISP_F16:
-        hipLaunchKernelGGL(dedisp_direct<__half>, dim3(static_cast<unsigned>(nblocks)), dim3(256), 0, s,
-                           static_cast<const __half*>(in), pitch, out, nsamp, dt->shift, p->ndm_pad, p->nchans,
-                           tblocks);
-        break;
-      default:
-        hipLaunchKernelGGL(dedisp_direct<float>, dim3(static_cast<unsigned>(nblocks)), dim3(256), 0, s,
-                           static_cast<const float*>(in), pitch, out, nsamp, dt->shift, p->ndm_pad, p->nchans,
-                           tblocks);
-    }
-    return DEDISP_HIP_STATUS(hipGetLastError());
-  }
-  // 8-bit and half input are widened into a stream-ordered workspace first
-  void* ws = nullptr;
-  bool own_ws = false;
-  if (p->dtype != DEDISP_F32) {
-    ws = ws_given;
-    if (ws == nullptr) {
-      const int64_t npad = widened_samples(total);
-      e = hipMallocAsync(&ws, static_cast<size_t>(npad) * staged_size(p->dtype), s);
-      if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
-      own_ws = true;
-    }
-    st = widen(p->dtype, in, ws, total, s);
-    if (st != DEDISP_OK) {
-      if (own_ws) (void)hipFreeAsync(ws, s);
-      return st;
+      case DEDISP_U8: return launch_direct<uint8_t>(p, dt, in, out, nsamp, s);
+      case DEDISP_F16: return launch_direct<__half>(p, dt, in, out, nsamp, s);
+      default: return launch_direct<float>(p, dt, in, out, nsamp, s);
     }
   }
-  TiledArgs a;
-  size_t lds = 0;
-  int64_t nblocks = 0;
-  int threads = 0;
-  st = tiled_args(p, v, ws ? ws : in, out, nsamp, &a, &lds, &nblocks, &threads);
-  const void* fn = kVariants[v - 1].fn[p->dtype];
-  if (st == DEDISP_OK && lds > 64 * 1024) st = allow_large_lds(fn);
-  if (st == DEDISP_OK) {
-    void* args[] = {&a};
-    st = DEDISP_HIP_STATUS(hipLaunchKernel(fn, dim3(static_cast<unsigned>(nblocks)), dim3(threads), args, lds, s));
+  if (p->dtype == DEDISP_F32) return launch_tiled(p, v, in, out, nsamp, s);
+  // 8-bit and half input are widened into a workspace first: the caller's,
+  // else a stream-ordered one
+  void* ws = ws_given;
+  if (ws == nullptr) {
+    st = keep_pool_memory(dev);
+    if (st != DEDISP_OK) return st;
+    e = hipMallocAsync(&ws, staged_bytes(p, nsamp), s);
+    if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
   }
-  if (own_ws) {
+  st = widen(p->dtype, in, ws, total, s);
+  if (st == DEDISP_OK) st = launch_tiled(p, v, ws, out, nsamp, s);
+  if (ws_given == nullptr) {
     const int st2 = DEDISP_HIP_STATUS(hipFreeAsync(ws, s));
     if (st == DEDISP_OK) st = st2;
   }
   return st;
+}
+
+int launch_staged(dedisp_plan p, int v, const void* staged, void* out, int64_t nsamp, hipStream_t s) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
+  DeviceTables* dt = nullptr;
+  int st = device_tables(p, dev, &dt);
+  if (st != DEDISP_OK) return st;
+  if (v > 0 && !offsets_fit(p, nsamp)) v = 0;
+  if (v == 0) {
+    // same channel order and float conversion as on raw input
+    if (p->dtype == DEDISP_U8) return launch_direct<uint16_t>(p, dt, staged, out, nsamp, s);
+    return launch_direct<float>(p, dt, staged, out, nsamp, s);
+  }
+  return launch_tiled(p, v, staged, out, nsamp, s);
+}
+
+size_t staged_bytes(dedisp_plan p, int64_t nsamp) {
+  return static_cast<size_t>(widened_samples((nsamp + p->max_shift) * p->nchans)) * staged_size(p->dtype);
+}
+
+int assemble(int dtype, const void* prev, const void* blk, void* dst, int64_t tail, int64_t block, int nchans,
+             bool zero_tail, hipStream_t s) {
+  if (nchans < 1 || tail < 0 || block < 1) return DEDISP_ERR_INVALID_ARG;
+  const int64_t pitch = tail + block;
+  const unsigned gx = static_cast<unsigned>(std::min<int64_t>((pitch + 255) / 256, 32));
+  const unsigned gy = static_cast<unsigned>(std::min(nchans, 65535));
+  const int z = zero_tail ? 1 : 0;
+  switch (dtype) {
+    case DEDISP_U8:
+      hipLaunchKernelGGL((assemble_window<uint8_t, uint16_t>), dim3(gx, gy), dim3(256), 0, s,
+                         static_cast<const uint16_t*>(prev), static_cast<const uint8_t*>(blk),
+                         static_cast<uint16_t*>(dst), tail, block, nchans, z);
+      break;
+    case DEDISP_F16:
+      hipLaunchKernelGGL((assemble_window<__half, float>), dim3(gx, gy), dim3(256), 0, s,
+                         static_cast<const float*>(prev), static_cast<const __half*>(blk), static_cast<float*>(dst),
+                         tail, block, nchans, z);
+      break;
+    case DEDISP_F32:
+      hipLaunchKernelGGL((assemble_window<float, float>), dim3(gx, gy), dim3(256), 0, s,
+                         static_cast<const float*>(prev), static_cast<const float*>(blk), static_cast<float*>(dst),
+                         tail, block, nchans, z);
+      break;
+    default:
+      return DEDISP_ERR_INVALID_ARG;
+  }
+  return DEDISP_HIP_STATUS(hipGetLastError());
 }
 
 int widen_jobs(const WidenJob* jobs, int njobs, hipStream_t s) {

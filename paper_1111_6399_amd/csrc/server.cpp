@@ -2,22 +2,24 @@
 // concurrently on a pool of streams; each beam keeps its last max_shift input
 // samples on the device so that consecutive blocks overlap correctly.
 //
-// Per beam there are two device buffers of [nchans][max_shift + B] samples.
-// Block b of a beam is assembled in buffer b%2: its first max_shift samples
-// per channel are copied from the end of buffer (b-1)%2 (zeros for the first
-// block), the new block is copied after them, and the plain de-dispersion
-// kernel runs over the buffer (nsamp = B output samples).  Every operation of
-// a beam goes to the same stream, so blocks of one beam run in order and a
-// buffer is not overwritten before the kernel two blocks back has read it;
-// different beams use different streams of the pool and overlap on the
-// device (copies of one beam under the kernels of others).
+// Per beam there are two device windows of [nchans][max_shift + B] samples in
+// staged form (8-bit samples widened to 16 bits, half to float, as the tiled
+// kernels read them) and one buffer for a raw block.  Block b of a beam is
+// copied as one contiguous transfer into the raw buffer; one kernel then
+// assembles window b%2: per channel the last max_shift samples of window
+// (b-1)%2 (zeros for the first block) followed by the new block widened.  The
+// de-dispersion kernel runs over that window directly (nsamp = B output
+// samples), so nothing is allocated or widened twice per block.  Every
+// operation of a beam goes to the same stream, so blocks of one beam run in
+// order and a window is not overwritten before the kernel two blocks back has
+// read it; different beams use different streams of the pool and overlap on
+// the device (copies of one beam under the kernels of others).
 //
-// Admission: a request needs its block and its output on the device
-// (nchans*B input samples + ndm*B outputs); it is admitted while the beams'
-// buffers plus the requests in flight fit the memory budget and fewer than
-// max_inflight requests are running.  Completion is recorded by a host
-// callback enqueued after the kernel, which also returns the request's
-// memory and slot.
+// Admission: a beam's windows and raw buffer are charged to the memory budget
+// when it is added; a request is charged its output (ndm*B values) and is
+// admitted while that fits the budget and fewer than max_inflight requests are
+// running.  Completion is recorded by a host callback enqueued after the
+// kernel, which also returns the request's charge and slot.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -57,7 +59,8 @@ struct Beam {
   int64_t block = 0;  // B
   int32_t tail = 0;   // max_shift
   size_t es = 1;
-  void* buf[2] = {nullptr, nullptr};
+  void* win[2] = {nullptr, nullptr};  // staged windows
+  void* raw = nullptr;                // one raw block
   size_t bytes = 0;
   int64_t next = 0;        // index of the next block
   bool zero_tail = true;   // next block starts from a zero history
@@ -152,15 +155,21 @@ extern "C" int dedisp_server_add_beam(dedisp_server s, dedisp_plan p, int64_t bl
   b.block = block_nsamp;
   b.tail = p->max_shift;
   b.es = dedisp::dtype_size(p->dtype);
-  const size_t one = static_cast<size_t>(p->nchans) * (b.tail + b.block) * b.es;
-  b.bytes = 2 * one;
+  const size_t win_bytes = dedisp::staged_bytes(p, block_nsamp);
+  const size_t raw_bytes = static_cast<size_t>(p->nchans) * b.block * b.es;
+  b.bytes = 2 * win_bytes + raw_bytes;
   std::lock_guard<std::mutex> g(s->mu);
   if (s->used.load() + b.bytes > s->budget) return DEDISP_ERR_AGAIN;
   hipError_t e = hipSetDevice(s->device);
-  if (e == hipSuccess) e = hipMalloc(&b.buf[0], one);
-  if (e == hipSuccess) e = hipMalloc(&b.buf[1], one);
+  if (e == hipSuccess) e = hipMalloc(&b.win[0], win_bytes);
+  if (e == hipSuccess) e = hipMalloc(&b.win[1], win_bytes);
+  if (e == hipSuccess) e = hipMalloc(&b.raw, raw_bytes);
+  // the padding after the last channel row is never written again
+  if (e == hipSuccess) e = hipMemset(b.win[0], 0, win_bytes);
+  if (e == hipSuccess) e = hipMemset(b.win[1], 0, win_bytes);
   if (e != hipSuccess) {
-    if (b.buf[0]) (void)hipFree(b.buf[0]);
+    for (void* x : {b.win[0], b.win[1], b.raw})
+      if (x) (void)hipFree(x);
     return DEDISP_HIP_STATUS(e);
   }
   b.stream = static_cast<int>(s->beams.size() % s->streams.size());
@@ -178,8 +187,7 @@ extern "C" int dedisp_submit(dedisp_server s, int beam_id, const void* block, vo
   Beam& b = s->beams[beam_id];
   const dedisp_plan p = b.plan;
   const size_t in_bytes = static_cast<size_t>(p->nchans) * b.block * b.es;
-  const size_t out_bytes = static_cast<size_t>(p->ndm) * b.block * 4;
-  const size_t footprint = in_bytes + out_bytes;
+  const size_t footprint = static_cast<size_t>(p->ndm) * b.block * 4;
   if (s->inflight.load() >= s->max_inflight || s->used.load() + footprint > s->budget) return DEDISP_ERR_AGAIN;
   hipError_t e = hipSetDevice(s->device);
   if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
@@ -208,25 +216,16 @@ extern "C" int dedisp_submit(dedisp_server s, int beam_id, const void* block, vo
   }
 
   hipStream_t st = s->streams[b.stream];
-  const int64_t pitch = b.tail + b.block;
-  const size_t row = static_cast<size_t>(pitch) * b.es;
-  char* dst = static_cast<char*>(b.buf[b.next & 1]);
-  const char* prev = static_cast<const char*>(b.buf[(b.next + 1) & 1]);
-  if (b.tail > 0) {
-    if (b.zero_tail)
-      e = hipMemset2DAsync(dst, row, 0, static_cast<size_t>(b.tail) * b.es, p->nchans, st);
-    else
-      e = hipMemcpy2DAsync(dst, row, prev + static_cast<size_t>(b.block) * b.es, row,
-                           static_cast<size_t>(b.tail) * b.es, p->nchans, hipMemcpyDeviceToDevice, st);
-  }
-  if (e == hipSuccess)
-    e = hipMemcpy2DAsync(dst + static_cast<size_t>(b.tail) * b.es, row, block, static_cast<size_t>(b.block) * b.es,
-                         static_cast<size_t>(b.block) * b.es, p->nchans, hipMemcpyDefault, st);
+  void* dst = b.win[b.next & 1];
+  const void* prev = b.win[(b.next + 1) & 1];
+  e = hipMemcpyAsync(b.raw, block, in_bytes, hipMemcpyDefault, st);
   int status = DEDISP_HIP_STATUS(e);
+  if (status == DEDISP_OK)
+    status = dedisp::assemble(p->dtype, prev, b.raw, dst, b.tail, b.block, p->nchans, b.zero_tail, st);
   if (status == DEDISP_OK) {
     int v = p->variant.load();
     if (v < 0) v = dedisp::default_variant(p);
-    status = dedisp::launch(p, v, dst, out_dev, b.block, st);
+    status = dedisp::launch_staged(p, v, dst, out_dev, b.block, st);
   }
   if (status == DEDISP_OK) status = DEDISP_HIP_STATUS(hipLaunchHostFunc(st, on_done, r.get()));
   if (status != DEDISP_OK) {
@@ -306,10 +305,9 @@ extern "C" int dedisp_server_destroy(dedisp_server s) {
   (void)dedisp_server_drain(s);
   int dev0 = -1;
   if (hipGetDevice(&dev0) == hipSuccess) (void)hipSetDevice(s->device);
-  for (Beam& b : s->beams) {
-    if (b.buf[0]) (void)hipFree(b.buf[0]);
-    if (b.buf[1]) (void)hipFree(b.buf[1]);
-  }
+  for (Beam& b : s->beams)
+    for (void* x : {b.win[0], b.win[1], b.raw})
+      if (x) (void)hipFree(x);
   for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
   if (dev0 >= 0) (void)hipSetDevice(dev0);
   delete s;

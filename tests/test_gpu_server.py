@@ -126,8 +126,10 @@ def test_admission_by_memory(dd):
     import torch
     band, dms, sh, m = beam_setup(7, 32, 16, 1.0, "f32", 512)
     plan = dd.Plan(32, band.f_top, band.df, band.tsamp, dms, "f32")
-    buf_bytes = 2 * 32 * (m + 512) * 4
-    # too small for the beam's history buffers
+    # two staged windows (padded to whole groups of 8 samples) and one raw block
+    total = 32 * (m + 512)
+    buf_bytes = 2 * ((total + 7) // 8 * 8) * 4 + 32 * 512 * 4
+    # too small for the beam's buffers
     s = dd.dedisp_server_create(buf_bytes - 1, 4)
     try:
         with pytest.raises(dd.DedispError) as e:
@@ -135,7 +137,7 @@ def test_admission_by_memory(dd):
         assert e.value.status == dd.DEDISP_ERR_AGAIN
     finally:
         dd.dedisp_server_destroy(s)
-    # room for the buffers but not for one request (block + output)
+    # room for the buffers but not for one request's output
     s = dd.dedisp_server_create(buf_bytes + 1000, 4)
     try:
         bid = dd.dedisp_server_add_beam(s, plan.handle, 512)
