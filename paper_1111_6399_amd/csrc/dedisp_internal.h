@@ -8,6 +8,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "../../include/dedisp.h"
@@ -43,27 +44,27 @@ struct TileShape {
 };
 
 // Per-device state of a plan: the delay table padded to a multiple of 64
-// trials per channel, and per tile shape the (min, max) delay of every
-// (trial tile, channel).
+// trials per channel, and the staging tables of the tiled kernels.
 struct DeviceTables {
-  int32_t* shift = nullptr;  // [nchans][ndm_pad]
-  std::map<int, int2*> windows;  // dms-per-tile -> [ntiles][nchans]
-  std::map<int64_t, int2*> geo;  // (dms-per-tile, samples per tile, pitch mod 4) -> [ntiles][nchans]
+  int32_t* shift = nullptr;  // [nchans + kShiftPadRows][ndm_pad]
+  // (trials per tile, samples per tile, align, bytes per staged sample, pitch) -> windows
+  std::map<std::tuple<int, int, int, int, int64_t>, uint32_t*> window_base;
+  // (trials per tile, align, bytes per staged sample, pitch mod align) -> slot positions
+  std::map<std::tuple<int, int, int, int64_t>, int32_t*> slot_pos;
 };
 
 // Arguments of one tiled launch (one beam); also the per-beam entry of the
 // batched launch's table.
 struct TiledArgs {
-  const void* in;
+  const void* in;  // staged input: float, or 8-bit widened to 16 bits
   int64_t pitch;   // samples per input row (nsamp + max_shift)
   int64_t total4;  // samples of the input in whole groups of 4
   void* out;
   int64_t nsamp;
-  const int32_t* shift;  // [nchans][ndm_pad]
-  const int32_t* win;    // [n_dm_tiles][nchans][2] (min, max) delay
-  const int32_t* geo;    // [n_dm_tiles][nchans + kGeoPad][2] (e, n4): window start and length (see device_geo)
-  int ndm, ndm_pad, nchans;
-  int zunits;  // 4-sample units per LDS slot (one channel of a stage)
+  const uint32_t* wbase;  // [n_dm_tiles][nchans + kGeoPad][2] staged byte offset of each window (less t0), 1 KB loads
+  const int32_t* spos;    // [n_dm_tiles][nchans + kGeoPad][trials per tile] byte position in the slot
+  int ndm, nchans;
+  int runs;  // 1 KB loads per LDS slot (one channel of a stage), the most any window needs
   int n_dm_tiles, n_t_tiles;
   int gd, gt;       // tiles per group along trials and time
   int n_dm_groups;  // groups along trials
@@ -110,16 +111,22 @@ namespace dedisp {
 
 // Device table of a plan on the current device (uploaded on first use).
 int device_tables(dedisp_plan p, int device, DeviceTables** out);
-// Window table for a trial-tile size on the current device.
-int device_windows(dedisp_plan p, int device, int dms_per_tile, const int2** out);
 const std::vector<int2>& host_windows(dedisp_plan p, int dms_per_tile);
-// Window geometry of every (trial tile, channel) for tiles of `samples`
-// samples (a multiple of align, 4 or 8) and rows whose length is `pitch_mod`
-// modulo align: e = (window start alignment) - (minimum delay), so that the
-// window of a tile starting at sample t0 begins at absolute sample
-// c*pitch + t0 - e (a multiple of align), and n4 = 4-sample units the window
-// spans.
-int device_geo(dedisp_plan p, int device, int dms_per_tile, int samples, int align, int pitch_mod, const int2** out);
+// Staging tables of the tiled kernels for tiles of `dms_per_tile` trials,
+// windows aligned to `align` samples (4 for float, 8 for 16-bit pairs) and
+// `es` bytes per staged sample.  A tile's window of channel c holds the
+// samples from c*pitch + t0 + lo - mis on (lo: smallest delay of the tile in
+// that channel, mis: alignment of c*pitch + t0 + lo, t0 a multiple of align):
+// window_base = (es * (c*pitch + lo - mis), loads): the byte offset of the
+// window (add es*t0 for the tile) and the 1 KB loads that cover what the
+// tile's reads reach (`samples` samples past the position of every trial,
+// plus 8 bytes), and slot_pos = es * (delay - lo + mis), the byte position of
+// a trial's first sample inside the window (its low bits give the alignment
+// of the trial).
+int device_window_base(dedisp_plan p, int device, int dms_per_tile, int samples, int align, int es, int64_t pitch,
+                       const uint32_t** out);
+int device_slot_pos(dedisp_plan p, int device, int dms_per_tile, int align, int es, int pitch_mod,
+                    const int32_t** out);
 
 // Kernel registry (kernels.hip).
 int variant_count();

@@ -227,21 +227,21 @@ __device__ __forceinline__ void lds_wait() {
 #define DD_U_AL2(a0, a1, x0, x1) DD_UA(a0, x0) DD_UA(a1, x1)
 #define DD_U_SH2(a0, a1, x0, x1) DD_UA(a0, x1) DD_UD(a1, x0)
 
-#define DD_BR2(P, EVEN, ODD)                           \
-  "s_bitcmp1_b32 %" #P ", 0\n\t"                      \
+#define DD_BR2(P, B, EVEN, ODD)                        \
+  "s_bitcmp1_b32 %" #P ", " #B "\n\t"                 \
   "s_cbranch_scc1 .Ldd_odd%=\n\t" EVEN "s_branch .Ldd_end%=\n" \
   ".Ldd_odd%=:\n\t"                                    \
   "s_nop 1\n\t" ODD ".Ldd_end%=:"
 
-#define DD_BR4(P, A0, A2, A1, A3)                                                      \
-  "s_bitcmp1_b32 %" #P ", 0\n\t"                                                      \
+#define DD_BR4(P, B0, B1, A0, A2, A1, A3)                                              \
+  "s_bitcmp1_b32 %" #P ", " #B0 "\n\t"                                               \
   "s_cbranch_scc1 .Ldd_o%=\n\t"                                                       \
-  "s_bitcmp1_b32 %" #P ", 1\n\t"                                                      \
+  "s_bitcmp1_b32 %" #P ", " #B1 "\n\t"                                               \
   "s_cbranch_scc1 .Ldd_2%=\n\t" A0 "s_branch .Ldd_end%=\n"                            \
   ".Ldd_2%=:\n\t"                                                                      \
   "s_nop 1\n\t" A2 "s_branch .Ldd_end%=\n"                                             \
   ".Ldd_o%=:\n\t"                                                                      \
-  "s_bitcmp1_b32 %" #P ", 1\n\t"                                                      \
+  "s_bitcmp1_b32 %" #P ", " #B1 "\n\t"                                               \
   "s_cbranch_scc1 .Ldd_3%=\n\t" A1 "s_branch .Ldd_end%=\n"                            \
   ".Ldd_3%=:\n\t"                                                                      \
   "s_nop 1\n\t" A3 ".Ldd_end%=:"
@@ -252,7 +252,7 @@ struct TrialAdds;
 template <>
 struct TrialAdds<8> {
   static __device__ __forceinline__ void f32(float* x, const v2u (&v)[8], int p) {
-    asm volatile(DD_BR2(32,
+    asm volatile(DD_BR2(32, 2,
                         DD_F_EVEN2(0, 1, 16, 17) DD_F_EVEN2(2, 3, 18, 19) DD_F_EVEN2(4, 5, 20, 21)
                             DD_F_EVEN2(6, 7, 22, 23) DD_F_EVEN2(8, 9, 24, 25) DD_F_EVEN2(10, 11, 26, 27)
                                 DD_F_EVEN2(12, 13, 28, 29) DD_F_EVEN2(14, 15, 30, 31),
@@ -272,7 +272,7 @@ struct TrialAdds<8> {
 template <>
 struct TrialAdds<4> {
   static __device__ __forceinline__ void f32(float* x, const v2u (&v)[4], int p) {
-    asm volatile(DD_BR2(16,
+    asm volatile(DD_BR2(16, 2,
                         DD_F_EVEN2(0, 1, 8, 9) DD_F_EVEN2(2, 3, 10, 11) DD_F_EVEN2(4, 5, 12, 13)
                             DD_F_EVEN2(6, 7, 14, 15),
                         DD_F_ODD2(0, 1, 8, 9) DD_F_ODD2(2, 3, 10, 11) DD_F_ODD2(4, 5, 12, 13)
@@ -285,7 +285,7 @@ struct TrialAdds<4> {
   }
   // e[0..7], o[0..7]
   static __device__ __forceinline__ void u8(uint32_t* e, uint32_t* o, const v2u (&v)[4], int p) {
-    asm volatile(DD_BR4(24,
+    asm volatile(DD_BR4(24, 1, 2,
                         DD_U_AL2(0, 1, 16, 17) DD_U_AL2(2, 3, 18, 19) DD_U_AL2(4, 5, 20, 21)
                             DD_U_AL2(6, 7, 22, 23),
                         DD_U_SH2(0, 1, 16, 17) DD_U_SH2(2, 3, 18, 19) DD_U_SH2(4, 5, 20, 21)
@@ -306,14 +306,14 @@ struct TrialAdds<4> {
 template <>
 struct TrialAdds<2> {
   static __device__ __forceinline__ void f32(float* x, const v2u (&v)[2], int p) {
-    asm volatile(DD_BR2(8, DD_F_EVEN2(0, 1, 4, 5) DD_F_EVEN2(2, 3, 6, 7),
+    asm volatile(DD_BR2(8, 2, DD_F_EVEN2(0, 1, 4, 5) DD_F_EVEN2(2, 3, 6, 7),
                         DD_F_ODD2(0, 1, 4, 5) DD_F_ODD2(2, 3, 6, 7))
                  : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3])
                  : "v"(v[0].x), "v"(v[0].y), "v"(v[1].x), "v"(v[1].y), "s"(p)
                  : "scc");
   }
   static __device__ __forceinline__ void u8(uint32_t* e, uint32_t* o, const v2u (&v)[2], int p) {
-    asm volatile(DD_BR4(12, DD_U_AL2(0, 1, 8, 9) DD_U_AL2(2, 3, 10, 11),
+    asm volatile(DD_BR4(12, 1, 2, DD_U_AL2(0, 1, 8, 9) DD_U_AL2(2, 3, 10, 11),
                         DD_U_SH2(0, 1, 8, 9) DD_U_SH2(2, 3, 10, 11),
                         DD_U_AL2(4, 5, 8, 9) DD_U_AL2(6, 7, 10, 11),
                         DD_U_SH2(4, 5, 8, 9) DD_U_SH2(6, 7, 10, 11))
@@ -346,16 +346,52 @@ __device__ __forceinline__ v4i buffer_words(const void* p, int64_t bytes) {
   return w;
 }
 
-// 16 bytes per lane from byte offset voff of the buffer straight into LDS at
-// lds + 16*lane (every lane).
-__device__ __forceinline__ void lds_dma16_all(uint32_t lds, uint32_t voff, const v4i& rs) {
-  asm volatile(
-      "s_mov_b32 m0, %[lds]\n\t"
-      "s_nop 0\n\t"
-      "buffer_load_dwordx4 %[vo], %[rs], 0 offen lds"
-      :
-      : [lds] "s"(lds), [vo] "v"(voff), [rs] "s"(rs)
-      : "memory");
+// K runs of 1 KB from the buffer straight into LDS: run m takes 16 bytes per
+// lane from byte offset voff + 1024*m to LDS byte lds + 1024*m + 16*lane (the
+// instruction's immediate offset moves both addresses, so the runs share one
+// M0 and one offset register).
+template <int K>
+__device__ __forceinline__ void lds_dma_runs(uint32_t lds, uint32_t voff, const v4i& rs) {
+  static_assert(K >= 1 && K <= 4, "immediate offsets stay below 4 KB");
+  if constexpr (K == 1)
+    asm volatile("s_mov_b32 m0, %[lds]\n\ts_nop 0\n\t"
+                 "buffer_load_dwordx4 %[vo], %[rs], 0 offen lds"
+                 :
+                 : [lds] "s"(lds), [vo] "v"(voff), [rs] "s"(rs)
+                 : "memory");
+  else if constexpr (K == 2)
+    asm volatile("s_mov_b32 m0, %[lds]\n\ts_nop 0\n\t"
+                 "buffer_load_dwordx4 %[vo], %[rs], 0 offen lds\n\t"
+                 "buffer_load_dwordx4 %[vo], %[rs], 0 offen offset:1024 lds"
+                 :
+                 : [lds] "s"(lds), [vo] "v"(voff), [rs] "s"(rs)
+                 : "memory");
+  else if constexpr (K == 3)
+    asm volatile("s_mov_b32 m0, %[lds]\n\ts_nop 0\n\t"
+                 "buffer_load_dwordx4 %[vo], %[rs], 0 offen lds\n\t"
+                 "buffer_load_dwordx4 %[vo], %[rs], 0 offen offset:1024 lds\n\t"
+                 "buffer_load_dwordx4 %[vo], %[rs], 0 offen offset:2048 lds"
+                 :
+                 : [lds] "s"(lds), [vo] "v"(voff), [rs] "s"(rs)
+                 : "memory");
+  else
+    asm volatile("s_mov_b32 m0, %[lds]\n\ts_nop 0\n\t"
+                 "buffer_load_dwordx4 %[vo], %[rs], 0 offen lds\n\t"
+                 "buffer_load_dwordx4 %[vo], %[rs], 0 offen offset:1024 lds\n\t"
+                 "buffer_load_dwordx4 %[vo], %[rs], 0 offen offset:2048 lds\n\t"
+                 "buffer_load_dwordx4 %[vo], %[rs], 0 offen offset:3072 lds"
+                 :
+                 : [lds] "s"(lds), [vo] "v"(voff), [rs] "s"(rs)
+                 : "memory");
+}
+
+// LDS read address of a (channel, trial) block: the lane's base plus the
+// trial's byte position in the slot with its alignment bits cleared (two
+// vector operations, so that no scalar instruction is spent on it).
+__device__ __forceinline__ uint32_t block_addr(uint32_t vbase, int q) {
+  uint32_t r;
+  asm volatile("v_and_b32_e64 %0, %1, -8\n\tv_add_u32 %0, %0, %2" : "=&v"(r) : "s"(q), "v"(vbase));
+  return r;
 }
 
 // Workgroup barrier after this wave's LDS writes have completed.  Writes that
@@ -366,26 +402,26 @@ __device__ __forceinline__ void lds_barrier_asm() {
 
 // Tile kernel body.  The input is staged by loads that write LDS directly
 // (no registers).  Float input (and half input widened to float beforehand)
-// is staged as float32, 16 bytes per 4 samples; 8-bit input, widened
-// beforehand to 16 bits, is staged as pairs of samples in the two 16-bit
-// halves of a word (8 bytes per 4 samples), so that one 32-bit add
-// accumulates two samples exactly (a half holds 256 channels of 255 before it
-// could carry).
+// is staged as float32, 4 bytes per sample; 8-bit input, widened beforehand
+// to 16 bits, is staged as pairs of samples in the two 16-bit halves of a
+// word, so that one 32-bit add accumulates two samples exactly (a half holds
+// 256 channels of 255 before it could carry).
 //
 // Channels are processed in stages of CG, two stages alternating in LDS (one
-// slot per channel).  The loads of a channel are issued by one group of NW/4
-// waves, the groups taking turns channel by channel; a group's waves split
-// the channel's window into runs of 1 KB (16 bytes per lane) and issue
-// exactly the runs the window needs.  A group issues the loads of a channel
-// of the next stage right after the barrier that frees its slot, and before
-// the barrier of that stage waits for all of its outstanding loads (it has no
-// other loads in flight: its next channel is at least 4 channels later, in a
-// later stage); the barrier then makes every load of the stage visible.  Only
-// the issuing waves do this work, so the scalar cost of staging is paid once
-// per run instead of once per wave.  One buffer descriptor covers the whole
-// input (32-bit byte offsets).  Window start and length come from a table
-// built on the host per (trial tile, channel); both it and the delay table
-// are padded so that reading a stage past the last channel needs no check.
+// slot per channel).  Channel c0 + g of every stage is loaded by the first
+// wave of group g (of NW/CG waves): right after the barrier that frees its
+// slot it issues the slot's 1 KB loads, and before the next barrier it waits
+// for them (it has nothing else in flight), so the barrier makes the stage
+// visible.  The scalar cost of staging is paid by one wave per channel.  A slot has room for the widest window of
+// the plan; each window takes the 1 KB loads that cover what its tile reads.
+// One buffer descriptor covers the whole input (32-bit byte offsets); loads
+// past its end return zeros.  Two tables built on the host give, per (trial
+// tile, channel), the byte offset of the window and its number of loads and,
+// per trial, the byte position of its first sample inside the slot, whose low
+// bits carry the alignment the adds need.
+// Both are padded past the last channel, so reading them a stage ahead needs
+// no check; the slots of channels past the last one are zeroed instead of
+// loaded, so adding them needs no check either.
 //
 // A (channel, trial) block reads its samples with aligned 64-bit reads,
 // several blocks of reads in flight.  Lanes 0-62 own the output samples; lane
@@ -403,14 +439,14 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
   constexpr int T = SPW * WT;
   constexpr int NR = kPairs ? KS / 2 : KS;  // 64-bit LDS reads per lane and block
   constexpr int ES = kPairs ? 2 : 4;        // bytes per staged sample
-  constexpr int UB = 4 * ES;                // LDS bytes per 4-sample unit
-  constexpr int G = 4;                      // issuing groups
-  constexpr int WPG = NW / G;               // waves per group
+  constexpr int WPG = NW / CG;              // waves per issuing group
   constexpr int NB = CG * DW;               // (channel, trial) blocks per stage
+  constexpr int QS = DW * WD;               // trials per tile (slot-position row length)
   constexpr int D = (3 - 1) * NR <= 15 ? 3 : 2;  // blocks with reads in flight
   constexpr int FLUSH = kPairs ? 256 : kChanBlock;
   static_assert(KS % 2 == 0 && (D - 1) * NR <= 15, "tile shape");
-  static_assert(NW % G == 0 && CG <= G && FLUSH % CG == 0, "stage shape");
+  static_assert(NW % CG == 0 && FLUSH % CG == 0, "stage shape");
+  static_assert((SPW * ES) % 8 == 0, "time offset of a wave keeps the read alignment");
   extern __shared__ float4 lds4[];
 
   const int tid = threadIdx.x;
@@ -418,22 +454,24 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
   const int lane = tid & 63;
   const int wd = wave % WD;
   const int wt = wave / WD;
-  const int grp = wave / WPG;   // issuing group of this wave
-  const int gq = wave % WPG;    // rank inside it
-  const int t0 = t_tile * T;    // the input is below 2^32 bytes, so are these indices
-  const int dw0 = dm_tile * (DW * WD) + wd * DW;
-  const int tw = wt * SPW;
+  const int grp = wave / WPG;  // channel of a stage this wave loads
+  const int gq = wave % WPG;   // rank inside its group
+  const int t0 = t_tile * T;   // the input is below 2^32 bytes, so are these indices
+  const int dw0 = dm_tile * QS + wd * DW;
   const int nchans = a.nchans;
-  const int pitch = static_cast<int>(a.pitch);
-  const uint32_t slot_bytes = static_cast<uint32_t>(a.zunits) * UB;
+  const int nstages = (nchans + CG - 1) / CG;
+  const uint32_t slot_bytes = 1024u * static_cast<uint32_t>(a.runs);
   const uint32_t lds0 = lds_addr(lds4);
-  const uint32_t vlane = lds0 + 8u * static_cast<uint32_t>(lane);
   const v4i rs = buffer_words(a.in, a.total4 * ES);
   const uint32_t lane16 = 16u * static_cast<uint32_t>(lane);
-  cint32* geo = (cint32*)(a.geo) + 2 * static_cast<int64_t>(dm_tile) * (nchans + kGeoPad);
+  // read base of the lane: its 8 bytes, and the wave's offset along time
+  const uint32_t vlane = lds0 + 8u * static_cast<uint32_t>(lane) + static_cast<uint32_t>(ES * SPW * wt);
+  const uint32_t t0b = static_cast<uint32_t>(ES * t0);
+  cint32* wb = (cint32*)(a.wbase) + 2 * (static_cast<int64_t>(dm_tile) * (nchans + kGeoPad) + grp);
+  cint32* sp = (cint32*)(a.spos) + static_cast<int64_t>(dm_tile) * (nchans + kGeoPad) * QS + wd * DW;
 
   // The last 1-3 samples of a float input (past the last whole group of 4)
-  // are read once here; the window holding them patches them in.  (Widened
+  // are read once here; the slot holding them patches them in.  (Widened
   // inputs are padded to whole groups.)
   float tail[3] = {0.f, 0.f, 0.f};
   int c_tail = nchans;  // first channel whose window can reach them
@@ -447,25 +485,41 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
     c_tail = lim < 0 ? 0 : static_cast<int>(lim / a.pitch) + 1;
   }
 
-  // This wave's share of the loads of channel c (window start e, length n4)
-  // if its group issues c: runs gq, gq + WPG, ... of the window, into LDS byte
-  // offset slot.
-  auto issue = [&](int c, int e, int n4, uint32_t slot) {
-    if ((c % G) != grp || c >= nchans) return;
-    const uint32_t base = ES * static_cast<uint32_t>(c * pitch + t0 - e) + lane16;
-    const int nruns = (n4 * UB + 1023) >> 10;
-    for (int i = gq; i < nruns; i += WPG) lds_dma16_all(lds0 + slot + 1024u * i, base + 1024u * i, rs);
+  // Loads of channel c (this group's channel of a stage: window offset wbase,
+  // `runs` loads) into the slot at LDS byte offset slot, issued by the
+  // group's first wave; a channel past the last one gets zeros instead.
+  auto issue = [&](int c, uint32_t wbase, int runs, uint32_t slot) {
+    if (gq != 0) return;
+    if (c < nchans) {
+      uint32_t lds = __builtin_amdgcn_readfirstlane(lds0 + slot);
+      uint32_t voff = wbase + t0b + lane16;
+      for (int i = 0; i < runs; i += 4, lds += 4096u, voff += 4096u) {
+        const int k = runs - i;
+        if (k >= 4)
+          lds_dma_runs<4>(lds, voff, rs);
+        else if (k == 3)
+          lds_dma_runs<3>(lds, voff, rs);
+        else if (k == 2)
+          lds_dma_runs<2>(lds, voff, rs);
+        else
+          lds_dma_runs<1>(lds, voff, rs);
+      }
+    } else if (c < nstages * CG) {
+      for (int m = 0; m < a.runs; ++m)
+        *reinterpret_cast<float4*>(reinterpret_cast<char*>(lds4) + slot + 1024u * m + lane16) =
+            make_float4(0.f, 0.f, 0.f, 0.f);
+    }
   };
-  // After this wave's loads of channel c landed: the partial last group of a
-  // float input, if the window holds it, is patched in by the wave and lane
-  // that loaded it.
-  auto patch = [&](int c, int e, int n4, uint32_t slot) {
-    if (kPairs || (c % G) != grp || c >= nchans || c < c_tail) return;
-    const int64_t a0 = static_cast<int64_t>(c) * pitch + t0 - e;
-    if (a0 + 4 * static_cast<int64_t>(n4) <= a.total4) return;
-    const int itail = static_cast<int>(a.total4 - a0) >> 2;
-    if (((itail >> 6) % WPG) == gq && lane == (itail & 63))
-      *reinterpret_cast<float4*>(reinterpret_cast<char*>(lds4) + slot + 16 * itail) =
+  // After the loads of channel c landed: the partial last group of a float
+  // input, if the slot holds it, is patched in by the lane that loaded its
+  // place.
+  auto patch = [&](int c, uint32_t wbase, int runs, uint32_t slot) {
+    if (kPairs || gq != 0 || c >= nchans || c < c_tail) return;
+    const int64_t off = static_cast<int64_t>(a.total4) * 4 - (static_cast<int64_t>(wbase) + t0b);
+    if (off < 0 || off >= 1024 * static_cast<int64_t>(runs)) return;
+    const uint32_t o = static_cast<uint32_t>(off);
+    if (lane == ((o >> 4) & 63))
+      *reinterpret_cast<float4*>(reinterpret_cast<char*>(lds4) + slot + o) =
           make_float4(tail[0], tail[1], tail[2], 0.f);
   };
 
@@ -514,62 +568,45 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
   };
 
   // Scalar state, read a stage ahead (the tables are padded past the last
-  // channel): geometry of the current, next and following stage, delays of
-  // the current and next stage.
-  int ce[CG], cn[CG], ne[CG], nn[CG], fe[CG], fn[CG];
-  int sh[CG][DW], shn[CG][DW];
-#pragma unroll
-  for (int u = 0; u < CG; ++u) {
-    ce[u] = geo[2 * u];
-    cn[u] = geo[2 * u + 1];
-    ne[u] = geo[2 * (CG + u)];
-    nn[u] = geo[2 * (CG + u) + 1];
-  }
-  cint32* gp = geo + 4 * CG;              // geometry of the stage after next
-  cint32* sp = (cint32*)(a.shift) + dw0;  // delays of the current stage
+  // channel): slot positions of the current and next stage, window offset of
+  // this group's channel in the next stage and the one after.
+  int q[CG][DW], qn[CG][DW];
 #pragma unroll
   for (int u = 0; u < CG; ++u)
 #pragma unroll
-    for (int j = 0; j < DW; ++j) sh[u][j] = sp[u * a.ndm_pad + j];
-  sp += CG * a.ndm_pad;
-#pragma unroll
-  for (int u = 0; u < CG; ++u) issue(u, ce[u], cn[u], u * slot_bytes);
+    for (int j = 0; j < DW; ++j) q[u][j] = sp[u * QS + j];
+  sp += CG * QS;
+  int wcur = wb[0], rcur = wb[1];                // this group's channel of stage 0
+  int wnext = wb[2 * CG], rnext = wb[2 * CG + 1];  // ... of stage 1
+  wb += 4 * CG;
+  issue(grp, static_cast<uint32_t>(wcur), rcur, grp * slot_bytes);
 
-  const int nstages = (nchans + CG - 1) / CG;
   for (int s = 0; s < nstages; ++s) {
     const int c0 = s * CG;
     const uint32_t sbase = (s & 1) ? CG * slot_bytes : 0u;
     wait_vm<0>();  // this wave's loads of the stage (if it issued any) are in LDS
-#pragma unroll
-    for (int u = 0; u < CG; ++u) patch(c0 + u, ce[u], cn[u], sbase + u * slot_bytes);
+    patch(c0 + grp, static_cast<uint32_t>(wcur), rcur, sbase + grp * slot_bytes);
     lds_barrier_asm();
-    // the other stage's slots are free: issue the next stage
-#pragma unroll
-    for (int u = 0; u < CG; ++u) issue(c0 + CG + u, ne[u], nn[u], (sbase ^ (CG * slot_bytes)) + u * slot_bytes);
+    // the other stage's slots are free: issue this group's channel of the next stage
+    issue(c0 + CG + grp, static_cast<uint32_t>(wnext), rnext, (sbase ^ (CG * slot_bytes)) + grp * slot_bytes);
 
     uint32_t ba[NB];
-    int pb[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int u = b / DW, j = b % DW;
-      const int p = sh[u][j] + ce[u] + tw;
-      pb[b] = p;
-      ba[b] = vlane + (sbase + u * slot_bytes +
-                       (kPairs ? 8u * static_cast<uint32_t>(p >> 2) : 4u * static_cast<uint32_t>(p & ~1)));
+      ba[b] = block_addr(vlane + sbase + u * slot_bytes, q[u][j]);
     }
     v2u rb[D][NR];
 #pragma unroll
     for (int b = 0; b < D && b < NB; ++b) lds_reads<NR>(ba[b], rb[b]);
     // scalar loads for later stages, consumed a stage from now
 #pragma unroll
-    for (int u = 0; u < CG; ++u) {
-      fe[u] = gp[2 * u];
-      fn[u] = gp[2 * u + 1];
+    for (int u = 0; u < CG; ++u)
 #pragma unroll
-      for (int j = 0; j < DW; ++j) shn[u][j] = sp[u * a.ndm_pad + j];
-    }
-    gp += 2 * CG;
-    sp += CG * a.ndm_pad;
+      for (int j = 0; j < DW; ++j) qn[u][j] = sp[u * QS + j];
+    sp += CG * QS;
+    const int wnn = wb[0], rnn = wb[1];
+    wb += 2 * CG;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int ahead = (NB - 1 - b) < (D - 1) ? (NB - 1 - b) : (D - 1);
@@ -579,25 +616,21 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
         lds_wait<NR>();
       else
         lds_wait<0>();
-      // a stage past the last channel reads stale LDS and adds nothing
-      if (b < DW || c0 + b / DW < nchans) {
-        if constexpr (kPairs)
-          TrialAdds<NR>::u8(acc0[b % DW], acc1[b % DW], rb[b % D], pb[b]);
-        else
-          TrialAdds<NR>::f32(acc0[b % DW], rb[b % D], pb[b]);
-      }
+      if constexpr (kPairs)
+        TrialAdds<NR>::u8(acc0[b % DW], acc1[b % DW], rb[b % D], q[b / DW][b % DW]);
+      else
+        TrialAdds<NR>::f32(acc0[b % DW], rb[b % D], q[b / DW][b % DW]);
       if (b + D < NB) lds_reads<NR>(ba[b + D], rb[(b + D) % D]);
     }
     if (((c0 + CG) % FLUSH) == 0) flush();
 #pragma unroll
-    for (int u = 0; u < CG; ++u) {
-      ce[u] = ne[u];
-      cn[u] = nn[u];
-      ne[u] = fe[u];
-      nn[u] = fn[u];
+    for (int u = 0; u < CG; ++u)
 #pragma unroll
-      for (int j = 0; j < DW; ++j) sh[u][j] = shn[u][j];
-    }
+      for (int j = 0; j < DW; ++j) q[u][j] = qn[u][j];
+    wcur = wnext;
+    rcur = rnext;
+    wnext = wnn;
+    rnext = rnn;
   }
   flush();       // the channels after the last whole flush block
   wait_vm<0>();  // no load may still be writing LDS when the workgroup ends
@@ -611,7 +644,7 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
     if constexpr (kPairs) {
 #pragma unroll
       for (int k = 0; k < NR; ++k) {
-        const int64_t t = static_cast<int64_t>(t0) + tw + 4 * lane + 252 * k;
+        const int64_t t = static_cast<int64_t>(t0) + wt * SPW + 4 * lane + 252 * k;
         int32_t* o = static_cast<int32_t*>(a.out) + d * nsamp + t;
         if (t + 3 < nsamp) {
           const int4 w4 = make_int4(static_cast<int32_t>(tot[j][4 * k]), static_cast<int32_t>(tot[j][4 * k + 1]),
@@ -626,7 +659,7 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
     } else {
 #pragma unroll
       for (int k = 0; k < NR; ++k) {
-        const int64_t t = static_cast<int64_t>(t0) + tw + 2 * lane + 126 * k;
+        const int64_t t = static_cast<int64_t>(t0) + wt * SPW + 2 * lane + 126 * k;
         float* o = static_cast<float*>(a.out) + d * nsamp + t;
         if (t + 1 < nsamp) {
           const float2 w2 = make_float2(tot[j][2 * k], tot[j][2 * k + 1]);
@@ -639,12 +672,6 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
   }
 }
 
-// One tile: 8-bit input (widened to 16 bits) as pairs, float and half
-// (widened to float) as float32.
-template <typename In, int DW, int KS, int WD, int WT, int CG>
-__device__ __forceinline__ void tile_body(const TiledArgs& a, int dm_tile, int t_tile) {
-  tile_dma<sizeof(In) == 1, DW, KS, WD, WT, CG>(a, dm_tile, t_tile);
-}
 
 // Widening of 8-bit input to 16 bits and of half input to float, into a
 // buffer padded with zeros to npad samples (a multiple of 8): 8 samples per
@@ -718,11 +745,13 @@ __global__ __launch_bounds__(256) void assemble_window(const St* __restrict__ pr
   }
 }
 
-template <typename In, int DW, int KS, int WD, int WT, int CG>
+// One launch of a tile variant: 8-bit input (widened to 16 bits) as pairs,
+// float and half input (widened to float) as float32.
+template <bool kPairs, int DW, int KS, int WD, int WT, int CG>
 __global__ __launch_bounds__(64 * WD * WT) void dedisp_tiled(const TiledArgs a) {
   int dm_tile, t_tile;
   if (!tile_of(a, dm_tile, t_tile)) return;  // padding block of the last group
-  tile_body<In, DW, KS, WD, WT, CG>(a, dm_tile, t_tile);
+  tile_dma<kPairs, DW, KS, WD, WT, CG>(a, dm_tile, t_tile);
 }
 
 // Widening of the inputs of a batch: blockIdx.y selects the job, the blocks
@@ -783,13 +812,11 @@ __global__ __launch_bounds__(64 * WD * WT) void dedisp_batch_persistent(const Ba
     const int dm_tile = (g % a.n_dm_groups) * a.gd + i % a.gd;
     const int t_tile = (g / a.n_dm_groups) * a.gt + i / a.gd;
     if (dm_tile < a.n_dm_tiles && t_tile < a.n_t_tiles) {
-      const int dt = ((cint32*)(b.dtype))[beam];
-      if (dt == DEDISP_F32)
-        tile_body<float, DW, KS, WD, WT, CG>(a, dm_tile, t_tile);
-      else if (dt == DEDISP_U8)
-        tile_body<uint8_t, DW, KS, WD, WT, CG>(a, dm_tile, t_tile);
+      // 8-bit input is staged as 16-bit pairs, half and float as float
+      if (((cint32*)(b.dtype))[beam] == DEDISP_U8)
+        tile_dma<true, DW, KS, WD, WT, CG>(a, dm_tile, t_tile);
       else
-        tile_body<__half, DW, KS, WD, WT, CG>(a, dm_tile, t_tile);
+        tile_dma<false, DW, KS, WD, WT, CG>(a, dm_tile, t_tile);
     }
     lds_barrier();  // every wave is done with this item's LDS before the next
   }
@@ -809,9 +836,9 @@ struct Variant {
 #define DEDISP_VARIANT(DW, KS, WD, WT, CG)                                                          \
   Variant {                                                                                        \
     TileShape{DW, KS, WD, WT}, CG,                                                                 \
-        {reinterpret_cast<const void*>(&dedisp_tiled<uint8_t, DW, KS, WD, WT, CG>),                 \
-         reinterpret_cast<const void*>(&dedisp_tiled<__half, DW, KS, WD, WT, CG>),                  \
-         reinterpret_cast<const void*>(&dedisp_tiled<float, DW, KS, WD, WT, CG>)},                  \
+        {reinterpret_cast<const void*>(&dedisp_tiled<true, DW, KS, WD, WT, CG>),                    \
+         reinterpret_cast<const void*>(&dedisp_tiled<false, DW, KS, WD, WT, CG>),                   \
+         reinterpret_cast<const void*>(&dedisp_tiled<false, DW, KS, WD, WT, CG>)},                  \
         reinterpret_cast<const void*>(&dedisp_batch_persistent<DW, KS, WD, WT, CG>)                 \
   }
 
@@ -831,23 +858,22 @@ constexpr int kNumTiled = sizeof(kVariants) / sizeof(kVariants[0]);
 
 constexpr size_t kMaxLds = 160 * 1024;
 
-// 4-sample units per LDS slot (one channel's window) a tiled variant needs
-// for this plan, or 0 if the plan's delay spread is too wide for the
-// variant's LDS.  A window covers the tile's samples, the delay spread of its
-// trials, the alignment of its start (to 4 samples for float staging, 8 for
-// 16-bit pairs) and the neighbour words read past the last sample; a slot has
-// one load (1 KB) of slack for the last run.  Two stages of `cg` slots are
-// live.
-int lds_units(dedisp_plan p, const Variant& v) {
+// 1 KB loads per LDS slot (one channel's window) a tiled variant needs for
+// this plan, or 0 if the plan's delay spread is too wide for the variant's
+// LDS.  A window covers the tile's samples, the delay spread of its trials,
+// the alignment of its start (to 4 samples for float staging, 8 for 16-bit
+// pairs) and the neighbour word the halo lane reads past the last sample.
+// Two stages of `cg` slots are live.
+int slot_runs(dedisp_plan p, const Variant& v) {
   const std::vector<int2>& w = host_windows(p, v.shape.dms());
   int spread = 0;
   for (const int2& x : w) spread = std::max(spread, x.y - x.x);
-  const int64_t unit = p->dtype == DEDISP_U8 ? 8 : 16;
+  const int64_t es = staged_size(p->dtype);
   const int64_t align = p->dtype == DEDISP_U8 ? 8 : 4;
-  const int64_t n4 = (align - 1 + static_cast<int64_t>(spread) + v.shape.samples() + 7) / 4;
-  const int64_t units = n4 + 1024 / unit;
-  if (2 * v.cg * units * unit > static_cast<int64_t>(kMaxLds) - 256) return 0;  // 256 B for static LDS
-  return static_cast<int>(units);
+  const int64_t bytes = es * (static_cast<int64_t>(spread) + align - 1 + v.shape.samples()) + 8;
+  const int64_t runs = (bytes + 1023) / 1024;
+  if (2 * v.cg * runs * 1024 > static_cast<int64_t>(kMaxLds) - 256) return 0;  // 256 B for static LDS
+  return static_cast<int>(runs);
 }
 
 // The tiled kernels address their input with 32-bit byte offsets, including
@@ -867,7 +893,7 @@ TileShape variant_shape(int v) { return kVariants[v - 1].shape; }
 bool variant_fits(dedisp_plan p, int v) {
   if (v == 0) return true;
   if (v < 0 || v > kNumTiled) return false;
-  return lds_units(p, kVariants[v - 1]) > 0;
+  return slot_runs(p, kVariants[v - 1]) > 0;
 }
 
 int default_variant(dedisp_plan p) {
@@ -1047,13 +1073,20 @@ int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, T
   int st = device_tables(p, dev, &dt);
   if (st != DEDISP_OK) return st;
   const Variant& var = kVariants[v - 1];
-  const int zunits = lds_units(p, var);
-  if (zunits == 0) return DEDISP_ERR_INVALID_ARG;
-  const int2* win = nullptr;
-  st = device_windows(p, dev, var.shape.dms(), &win);
-  if (st != DEDISP_OK) return st;
+  const int runs = slot_runs(p, var);
+  if (runs == 0) return DEDISP_ERR_INVALID_ARG;
+  // the tiled kernels address the input with 32-bit byte offsets
+  if (!offsets_fit(p, nsamp)) return DEDISP_ERR_INVALID_ARG;
   const int64_t pitch = nsamp + p->max_shift;
   const int64_t total = pitch * p->nchans;
+  const int align = p->dtype == DEDISP_U8 ? 8 : 4;
+  const int es = static_cast<int>(staged_size(p->dtype));
+  const uint32_t* wbase = nullptr;
+  st = device_window_base(p, dev, var.shape.dms(), var.shape.samples(), align, es, pitch, &wbase);
+  if (st != DEDISP_OK) return st;
+  const int32_t* spos = nullptr;
+  st = device_slot_pos(p, dev, var.shape.dms(), align, es, static_cast<int>(pitch % align), &spos);
+  if (st != DEDISP_OK) return st;
   TiledArgs& a = *ap;
   a.in = in;
   a.pitch = pitch;
@@ -1067,22 +1100,11 @@ int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, T
   a.max_shift = p->max_shift;
   a.out = out;
   a.nsamp = nsamp;
-  a.shift = dt->shift;
-  a.win = reinterpret_cast<const int32_t*>(win);
-  a.geo = nullptr;
-  {
-    // the tiled kernels address the input with 32-bit byte offsets
-    if (!offsets_fit(p, nsamp)) return DEDISP_ERR_INVALID_ARG;
-    const int2* geo = nullptr;
-    const int align = p->dtype == DEDISP_U8 ? 8 : 4;
-    st = device_geo(p, dev, var.shape.dms(), var.shape.samples(), align, static_cast<int>(pitch % align), &geo);
-    if (st != DEDISP_OK) return st;
-    a.geo = reinterpret_cast<const int32_t*>(geo);
-  }
+  a.wbase = wbase;
+  a.spos = spos;
+  a.runs = runs;
   a.ndm = p->ndm;
-  a.ndm_pad = p->ndm_pad;
   a.nchans = p->nchans;
-  a.zunits = zunits;
   a.n_dm_tiles = (p->ndm + var.shape.dms() - 1) / var.shape.dms();
   const int64_t n_t_tiles = (nsamp + var.shape.samples() - 1) / var.shape.samples();
   if (n_t_tiles > INT32_MAX / 64) return DEDISP_ERR_INVALID_ARG;
@@ -1095,7 +1117,7 @@ int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, T
   // a multiple of 8 groups, so that every XCD's run of blocks is whole groups
   const int64_t nblocks = (n_groups + 7) / 8 * 8 * a.gd * a.gt;
   if (nblocks > INT32_MAX) return DEDISP_ERR_INVALID_ARG;
-  *lds_out = 2 * static_cast<size_t>(var.cg) * zunits * (p->dtype == DEDISP_U8 ? 8 : 16);
+  *lds_out = 2 * static_cast<size_t>(var.cg) * runs * 1024;
   *nblocks_out = nblocks;
   *threads_out = var.shape.threads();
   return DEDISP_OK;
@@ -1127,16 +1149,16 @@ int prepare(dedisp_plan p, int v, int64_t nsamp) {
   DeviceTables* dt = nullptr;
   int st = device_tables(p, dev, &dt);
   if (st != DEDISP_OK || v <= 0) return st;
-  const int2* w = nullptr;
-  st = device_windows(p, dev, variant_shape(v).dms(), &w);
+  const int64_t pitch = nsamp + p->max_shift;
+  const int align = p->dtype == DEDISP_U8 ? 8 : 4;
+  const int es = static_cast<int>(staged_size(p->dtype));
+  const int dms = variant_shape(v).dms();
+  const uint32_t* wbase = nullptr;
+  st = device_window_base(p, dev, dms, variant_shape(v).samples(), align, es, pitch, &wbase);
   if (st != DEDISP_OK) return st;
-  {
-    const int2* g = nullptr;
-    const int align = p->dtype == DEDISP_U8 ? 8 : 4;
-    st = device_geo(p, dev, variant_shape(v).dms(), variant_shape(v).samples(), align,
-                    static_cast<int>((nsamp + p->max_shift) % align), &g);
-    if (st != DEDISP_OK) return st;
-  }
+  const int32_t* spos = nullptr;
+  st = device_slot_pos(p, dev, dms, align, es, static_cast<int>(pitch % align), &spos);
+  if (st != DEDISP_OK) return st;
   return allow_large_lds(kVariants[v - 1].fn[p->dtype]);
 }
 

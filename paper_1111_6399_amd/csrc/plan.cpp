@@ -68,8 +68,8 @@ extern "C" int dedisp_plan_destroy(dedisp_plan p) {
   for (auto& kv : p->dev) {
     if (hipSetDevice(kv.first) != hipSuccess) continue;
     if (kv.second.shift) (void)hipFree(kv.second.shift);
-    for (auto& w : kv.second.windows) (void)hipFree(w.second);
-    for (auto& w : kv.second.geo) (void)hipFree(w.second);
+    for (auto& w : kv.second.window_base) (void)hipFree(w.second);
+    for (auto& w : kv.second.slot_pos) (void)hipFree(w.second);
   }
   if (dev0 >= 0) (void)hipSetDevice(dev0);
   delete p;
@@ -172,55 +172,90 @@ int device_tables(dedisp_plan p, int device, DeviceTables** out) {
   return DEDISP_OK;
 }
 
-int device_windows(dedisp_plan p, int device, int dms_per_tile, const int2** out) {
+namespace {
+
+template <typename T>
+int upload(const std::vector<T>& h, T** out) {
+  T* dptr = nullptr;
+  hipError_t e = hipMalloc(&dptr, h.size() * sizeof(T));
+  if (e != hipSuccess) return hip_status(e);
+  e = hipMemcpy(dptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(dptr);
+    return hip_status(e);
+  }
+  *out = dptr;
+  return DEDISP_OK;
+}
+
+// Alignment of the window start c*pitch + t0 + lo (t0 is a multiple of align).
+inline int window_mis(int c, int64_t pitch, int lo, int align) {
+  return static_cast<int>((static_cast<int64_t>(c) * (pitch % align) + lo) % align);
+}
+
+}  // namespace
+
+int device_window_base(dedisp_plan p, int device, int dms_per_tile, int samples, int align, int es, int64_t pitch,
+                       const uint32_t** out) {
   const std::vector<int2>& hw = host_windows(p, dms_per_tile);
   std::lock_guard<std::mutex> g(p->mu);
   DeviceTables& t = p->dev[device];
-  auto it = t.windows.find(dms_per_tile);
-  if (it == t.windows.end()) {
-    int2* dptr = nullptr;
-    hipError_t e = hipMalloc(&dptr, hw.size() * sizeof(int2));
-    if (e != hipSuccess) return hip_status(e);
-    e = hipMemcpy(dptr, hw.data(), hw.size() * sizeof(int2), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-      (void)hipFree(dptr);
-      return hip_status(e);
-    }
-    it = t.windows.emplace(dms_per_tile, dptr).first;
+  const auto key = std::make_tuple(dms_per_tile, samples, align, es, pitch);
+  auto it = t.window_base.find(key);
+  if (it == t.window_base.end()) {
+    const int ntiles = static_cast<int>(hw.size() / p->nchans);
+    const int stride = p->nchans + kGeoPad;
+    // rows of each tile end with kGeoPad zero entries: kernels read the
+    // entries of channels ahead without a bounds check
+    std::vector<uint32_t> base(2 * static_cast<size_t>(ntiles) * stride, 0u);
+    for (int tile = 0; tile < ntiles; ++tile)
+      for (int c = 0; c < p->nchans; ++c) {
+        const int2 w = hw[static_cast<size_t>(tile) * p->nchans + c];
+        const int mis = window_mis(c, pitch, w.x, align);
+        const int64_t start = static_cast<int64_t>(c) * pitch + w.x - mis;
+        // bytes the tile's reads reach: its samples, the delay spread, the
+        // start alignment and the halo lane's neighbour word
+        const int64_t bytes = es * (static_cast<int64_t>(w.y) - w.x + mis + samples) + 8;
+        uint32_t* e = base.data() + 2 * (static_cast<size_t>(tile) * stride + c);
+        e[0] = static_cast<uint32_t>(es * start);
+        e[1] = static_cast<uint32_t>((bytes + 1023) / 1024);
+      }
+    uint32_t* d = nullptr;
+    const int st = upload(base, &d);
+    if (st != DEDISP_OK) return st;
+    it = t.window_base.emplace(key, d).first;
   }
   *out = it->second;
   return DEDISP_OK;
 }
 
-int device_geo(dedisp_plan p, int device, int dms_per_tile, int samples, int align, int pitch_mod, const int2** out) {
+int device_slot_pos(dedisp_plan p, int device, int dms_per_tile, int align, int es, int pitch_mod,
+                    const int32_t** out) {
   const std::vector<int2>& hw = host_windows(p, dms_per_tile);
-  const int64_t key = (static_cast<int64_t>(dms_per_tile) << 40) | (static_cast<int64_t>(samples) << 12) |
-                      (static_cast<int64_t>(align) << 4) | pitch_mod;
   std::lock_guard<std::mutex> g(p->mu);
   DeviceTables& t = p->dev[device];
-  auto it = t.geo.find(key);
-  if (it == t.geo.end()) {
+  const auto key = std::make_tuple(dms_per_tile, align, es, static_cast<int64_t>(pitch_mod));
+  auto it = t.slot_pos.find(key);
+  if (it == t.slot_pos.end()) {
     const int ntiles = static_cast<int>(hw.size() / p->nchans);
-    const int stride = p->nchans + kGeoPad;
-    // each tile's row ends with kGeoPad zero entries: kernels read the
-    // windows of channels ahead without a bounds check
-    std::vector<int2> geo(static_cast<size_t>(ntiles) * stride, make_int2(0, 0));
+    const size_t stride = static_cast<size_t>(p->nchans + kGeoPad) * dms_per_tile;
+    std::vector<int32_t> pos(static_cast<size_t>(ntiles) * stride, 0);
     for (int tile = 0; tile < ntiles; ++tile)
       for (int c = 0; c < p->nchans; ++c) {
-        const int2 w = hw[static_cast<size_t>(tile) * p->nchans + c];
-        // alignment of the window start c*pitch + t0 + lo (t0 is a multiple of align)
-        const int mis = static_cast<int>((static_cast<int64_t>(c) * pitch_mod + w.x) % align);
-        geo[static_cast<size_t>(tile) * stride + c] = make_int2(mis - w.x, (mis + (w.y - w.x) + samples + 7) >> 2);
+        const int lo = hw[static_cast<size_t>(tile) * p->nchans + c].x;
+        const int mis = window_mis(c, pitch_mod, lo, align);
+        const int32_t* row = p->shift.data() + static_cast<size_t>(c) * p->ndm;
+        int32_t* dst = pos.data() + tile * stride + static_cast<size_t>(c) * dms_per_tile;
+        for (int j = 0; j < dms_per_tile; ++j) {
+          // trials past the last repeat it, so that they stay inside the window
+          const int d = std::min(p->ndm - 1, tile * dms_per_tile + j);
+          dst[j] = es * (row[d] - lo + mis);
+        }
       }
-    int2* dptr = nullptr;
-    hipError_t e = hipMalloc(&dptr, geo.size() * sizeof(int2));
-    if (e != hipSuccess) return hip_status(e);
-    e = hipMemcpy(dptr, geo.data(), geo.size() * sizeof(int2), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-      (void)hipFree(dptr);
-      return hip_status(e);
-    }
-    it = t.geo.emplace(key, dptr).first;
+    int32_t* d = nullptr;
+    const int st = upload(pos, &d);
+    if (st != DEDISP_OK) return st;
+    it = t.slot_pos.emplace(key, d).first;
   }
   *out = it->second;
   return DEDISP_OK;
