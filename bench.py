@@ -279,7 +279,7 @@ def run_served(args) -> dict:
     log("served: %d beams, %d blocks over %.0f s (offered %.1f blocks/s = %.3g adds/s)"
         % (nbeams, len(arrivals), horizon, len(arrivals) / horizon, work * len(arrivals) / horizon))
 
-    def replay(submit, poll_done, nslots):
+    def replay(submit, poll_done, nslots, label):
         """Drive one arrival schedule; submit(beam, blk, out) -> handle or None;
         poll_done(handle) -> bool.  Returns latencies of blocks arriving after
         the warm-up, the completion span and the largest backlog."""
@@ -289,8 +289,13 @@ def run_served(args) -> dict:
         t_start = time.perf_counter() + 0.05
         i, max_backlog, overload = 0, 0, False
         first_done = last_done = None
+        next_report = 15.0
         while i < len(arrivals) or backlog or running:
             now = time.perf_counter() - t_start
+            if now >= next_report:
+                log("  %s: %.0f s, %d of %d blocks arrived, %d done, backlog %d"
+                    % (label, now, i, len(arrivals), len(lat), len(backlog)))
+                next_report += 15.0
             while i < len(arrivals) and arrivals[i][0] <= now:
                 backlog.append(arrivals[i])
                 i += 1
@@ -353,7 +358,7 @@ def run_served(args) -> dict:
         def s_poll(tk):
             return dd.dedisp_poll(server, tk)[0]
 
-        lat, span, backlog = replay(s_submit, s_poll, args.inflight)
+        lat, span, backlog = replay(s_submit, s_poll, args.inflight, "served")
         dd.dedisp_server_drain(server)
         p50s, p99s, rate_s = dd.dedisp_server_stats(server)
     finally:
@@ -379,7 +384,7 @@ def run_served(args) -> dict:
             ev.record(stream)
         return ev
 
-    lat, span, backlog = replay(p_submit, lambda ev: ev.query(), 1)
+    lat, span, backlog = replay(p_submit, lambda ev: ev.query(), 1, "plain FIFO")
     torch.cuda.synchronize()
     plain = summary(lat, span, backlog, "plain FIFO")
     hist.clear()
