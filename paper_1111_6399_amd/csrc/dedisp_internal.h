@@ -47,7 +47,7 @@ struct TileShape {
 // trials per channel, and the staging tables of the tiled kernels.
 struct DeviceTables {
   int32_t* shift = nullptr;  // [nchans + kShiftPadRows][ndm_pad]
-  // (trials per tile, samples per tile, align, bytes per staged sample, pitch) -> windows
+  // (trials per tile, samples per tile, align, bytes per staged sample, pitch mod align) -> windows
   std::map<std::tuple<int, int, int, int, int64_t>, uint32_t*> window_base;
   // (trials per tile, align, bytes per staged sample, pitch mod align) -> slot positions
   std::map<std::tuple<int, int, int, int64_t>, int32_t*> slot_pos;
@@ -61,7 +61,7 @@ struct TiledArgs {
   int64_t total4;  // samples of the input in whole groups of 4
   void* out;
   int64_t nsamp;
-  const uint32_t* wbase;  // [n_dm_tiles][nchans + kGeoPad][2] staged byte offset of each window (less t0), 1 KB loads
+  const uint32_t* wbase;  // [n_dm_tiles][nchans + kGeoPad][2] byte offset of each window from its row's aligned start (less t0), 1 KB loads
   const int32_t* spos;    // [n_dm_tiles][nchans + kGeoPad][trials per tile] byte position in the slot
   int ndm, nchans;
   int runs;  // 1 KB loads per LDS slot (one channel of a stage), the most any window needs
@@ -117,13 +117,14 @@ const std::vector<int2>& host_windows(dedisp_plan p, int dms_per_tile);
 // `es` bytes per staged sample.  A tile's window of channel c holds the
 // samples from c*pitch + t0 + lo - mis on (lo: smallest delay of the tile in
 // that channel, mis: alignment of c*pitch + t0 + lo, t0 a multiple of align):
-// window_base = (es * (c*pitch + lo - mis), loads): the byte offset of the
-// window (add es*t0 for the tile) and the 1 KB loads that cover what the
-// tile's reads reach (`samples` samples past the position of every trial,
-// plus 8 bytes), and slot_pos = es * (delay - lo + mis), the byte position of
-// a trial's first sample inside the window (its low bits give the alignment
-// of the trial).
-int device_window_base(dedisp_plan p, int device, int dms_per_tile, int samples, int align, int es, int64_t pitch,
+// window_base = (es * ((c*pitch mod align) + lo - mis), loads): the byte
+// offset of the window from the start of row c rounded down to align (add
+// es*t0 for the tile) and the 1 KB loads that cover what the tile's reads
+// reach (`samples` samples past the position of every trial, plus 8 bytes),
+// and slot_pos = es * (delay - lo + mis), the byte position of a trial's
+// first sample inside the window (its low bits give the alignment of the
+// trial).  Both depend on the row length only through pitch mod align.
+int device_window_base(dedisp_plan p, int device, int dms_per_tile, int samples, int align, int es, int pitch_mod,
                        const uint32_t** out);
 int device_slot_pos(dedisp_plan p, int device, int dms_per_tile, int align, int es, int pitch_mod,
                     const int32_t** out);

@@ -335,13 +335,15 @@ __device__ __forceinline__ void wait_vm() {
 }
 
 // Buffer descriptor words for `bytes` bytes from `p` (raw buffer, range
-// checked: reads past the end return zero without touching memory).
+// checked: reads past the end return zero without touching memory; more than
+// 2^32 - 1 bytes are clamped to that).
 __device__ __forceinline__ v4i buffer_words(const void* p, int64_t bytes) {
   const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t n = bytes >= 0xffffffffll ? 0xffffffffu : static_cast<uint32_t>(bytes < 0 ? 0 : bytes);
   v4i w;  // wave-uniform by construction; made explicit for the scalar operands of inline assembly
   w.x = __builtin_amdgcn_readfirstlane(static_cast<int>(a & 0xffffffffu));
   w.y = __builtin_amdgcn_readfirstlane(static_cast<int>((a >> 32) & 0xffffu));
-  w.z = __builtin_amdgcn_readfirstlane(static_cast<int>(bytes));
+  w.z = __builtin_amdgcn_readfirstlane(static_cast<int>(n));
   w.w = 0x00020000;
   return w;
 }
@@ -414,8 +416,10 @@ __device__ __forceinline__ void lds_barrier_asm() {
 // for them (it has nothing else in flight), so the barrier makes the stage
 // visible.  The scalar cost of staging is paid by one wave per channel.  A slot has room for the widest window of
 // the plan; each window takes the 1 KB loads that cover what its tile reads.
-// One buffer descriptor covers the whole input (32-bit byte offsets); loads
-// past its end return zeros.  Two tables built on the host give, per (trial
+// The loads of a channel go through a buffer descriptor based at its row
+// (rounded down to 16 bytes) that reaches to the end of the input, so offsets
+// stay 32-bit however large the input is, and loads past its end return
+// zeros.  Two tables built on the host give, per (trial
 // tile, channel), the byte offset of the window and its number of loads and,
 // per trial, the byte position of its first sample inside the slot, whose low
 // bits carry the alignment the adds need.
@@ -456,13 +460,13 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
   const int wt = wave / WD;
   const int grp = wave / WPG;  // channel of a stage this wave loads
   const int gq = wave % WPG;   // rank inside its group
-  const int t0 = t_tile * T;   // the input is below 2^32 bytes, so are these indices
+  const int t0 = t_tile * T;   // rows are below 2^32 bytes, so are these indices
   const int dw0 = dm_tile * QS + wd * DW;
   const int nchans = a.nchans;
   const int nstages = (nchans + CG - 1) / CG;
   const uint32_t slot_bytes = 1024u * static_cast<uint32_t>(a.runs);
   const uint32_t lds0 = lds_addr(lds4);
-  const v4i rs = buffer_words(a.in, a.total4 * ES);
+  constexpr int ALIGN = kPairs ? 8 : 4;     // window starts are aligned to 16 bytes
   const uint32_t lane16 = 16u * static_cast<uint32_t>(lane);
   // read base of the lane: its 8 bytes, and the wave's offset along time
   const uint32_t vlane = lds0 + 8u * static_cast<uint32_t>(lane) + static_cast<uint32_t>(ES * SPW * wt);
@@ -485,12 +489,19 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
     c_tail = lim < 0 ? 0 : static_cast<int>(lim / a.pitch) + 1;
   }
 
-  // Loads of channel c (this group's channel of a stage: window offset wbase,
-  // `runs` loads) into the slot at LDS byte offset slot, issued by the
-  // group's first wave; a channel past the last one gets zeros instead.
+  // Byte offset of the aligned start of row c, where its descriptor is based.
+  auto row_base = [&](int c) -> int64_t {
+    return ES * ((static_cast<int64_t>(c) * a.pitch) & ~static_cast<int64_t>(ALIGN - 1));
+  };
+  // Loads of channel c (this group's channel of a stage: window offset wbase
+  // from its row base, `runs` loads) into the slot at LDS byte offset slot,
+  // issued by the group's first wave; a channel past the last one gets zeros
+  // instead.
   auto issue = [&](int c, uint32_t wbase, int runs, uint32_t slot) {
     if (gq != 0) return;
     if (c < nchans) {
+      const int64_t rb = row_base(c);
+      const v4i rs = buffer_words(static_cast<const char*>(a.in) + rb, a.total4 * ES - rb);
       uint32_t lds = __builtin_amdgcn_readfirstlane(lds0 + slot);
       uint32_t voff = wbase + t0b + lane16;
       for (int i = 0; i < runs; i += 4, lds += 4096u, voff += 4096u) {
@@ -515,7 +526,7 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
   // place.
   auto patch = [&](int c, uint32_t wbase, int runs, uint32_t slot) {
     if (kPairs || gq != 0 || c >= nchans || c < c_tail) return;
-    const int64_t off = static_cast<int64_t>(a.total4) * 4 - (static_cast<int64_t>(wbase) + t0b);
+    const int64_t off = static_cast<int64_t>(a.total4) * 4 - (row_base(c) + wbase + t0b);
     if (off < 0 || off >= 1024 * static_cast<int64_t>(runs)) return;
     const uint32_t o = static_cast<uint32_t>(off);
     if (lane == ((o >> 4) & 63))
@@ -876,12 +887,11 @@ int slot_runs(dedisp_plan p, const Variant& v) {
   return static_cast<int>(runs);
 }
 
-// The tiled kernels address their input with 32-bit byte offsets, including
-// the rows they read ahead past the last channel.
+// The tiled kernels address a row (and a window past its end) with 32-bit
+// byte offsets from the row's start.
 bool offsets_fit(dedisp_plan p, int64_t nsamp) {
   const int64_t pitch = nsamp + p->max_shift;
-  return (static_cast<int64_t>(p->nchans) + 16) * pitch * staged_size(p->dtype) + (static_cast<int64_t>(1) << 24) <
-         (static_cast<int64_t>(1) << 32);
+  return (pitch + 16) * staged_size(p->dtype) + (static_cast<int64_t>(1) << 20) < (static_cast<int64_t>(1) << 32);
 }
 
 }  // namespace
@@ -962,8 +972,8 @@ int launch(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, hipSt
   int st = device_tables(p, dev, &dt);
   if (st != DEDISP_OK) return st;
   const int64_t total = (nsamp + p->max_shift) * p->nchans;
-  // the tiled kernels address their input with 32-bit byte offsets; larger
-  // inputs take the direct kernel
+  // the tiled kernels address each row with 32-bit byte offsets; longer rows
+  // take the direct kernel
   if (v > 0 && !offsets_fit(p, nsamp)) v = 0;
   if (v == 0) {
     switch (p->dtype) {
@@ -1075,14 +1085,14 @@ int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, T
   const Variant& var = kVariants[v - 1];
   const int runs = slot_runs(p, var);
   if (runs == 0) return DEDISP_ERR_INVALID_ARG;
-  // the tiled kernels address the input with 32-bit byte offsets
+  // the tiled kernels address each row with 32-bit byte offsets
   if (!offsets_fit(p, nsamp)) return DEDISP_ERR_INVALID_ARG;
   const int64_t pitch = nsamp + p->max_shift;
   const int64_t total = pitch * p->nchans;
   const int align = p->dtype == DEDISP_U8 ? 8 : 4;
   const int es = static_cast<int>(staged_size(p->dtype));
   const uint32_t* wbase = nullptr;
-  st = device_window_base(p, dev, var.shape.dms(), var.shape.samples(), align, es, pitch, &wbase);
+  st = device_window_base(p, dev, var.shape.dms(), var.shape.samples(), align, es, static_cast<int>(pitch % align), &wbase);
   if (st != DEDISP_OK) return st;
   const int32_t* spos = nullptr;
   st = device_slot_pos(p, dev, var.shape.dms(), align, es, static_cast<int>(pitch % align), &spos);
@@ -1154,7 +1164,7 @@ int prepare(dedisp_plan p, int v, int64_t nsamp) {
   const int es = static_cast<int>(staged_size(p->dtype));
   const int dms = variant_shape(v).dms();
   const uint32_t* wbase = nullptr;
-  st = device_window_base(p, dev, dms, variant_shape(v).samples(), align, es, pitch, &wbase);
+  st = device_window_base(p, dev, dms, variant_shape(v).samples(), align, es, static_cast<int>(pitch % align), &wbase);
   if (st != DEDISP_OK) return st;
   const int32_t* spos = nullptr;
   st = device_slot_pos(p, dev, dms, align, es, static_cast<int>(pitch % align), &spos);

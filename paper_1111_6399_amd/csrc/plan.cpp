@@ -195,12 +195,12 @@ inline int window_mis(int c, int64_t pitch, int lo, int align) {
 
 }  // namespace
 
-int device_window_base(dedisp_plan p, int device, int dms_per_tile, int samples, int align, int es, int64_t pitch,
+int device_window_base(dedisp_plan p, int device, int dms_per_tile, int samples, int align, int es, int pitch_mod,
                        const uint32_t** out) {
   const std::vector<int2>& hw = host_windows(p, dms_per_tile);
   std::lock_guard<std::mutex> g(p->mu);
   DeviceTables& t = p->dev[device];
-  const auto key = std::make_tuple(dms_per_tile, samples, align, es, pitch);
+  const auto key = std::make_tuple(dms_per_tile, samples, align, es, static_cast<int64_t>(pitch_mod));
   auto it = t.window_base.find(key);
   if (it == t.window_base.end()) {
     const int ntiles = static_cast<int>(hw.size() / p->nchans);
@@ -211,8 +211,9 @@ int device_window_base(dedisp_plan p, int device, int dms_per_tile, int samples,
     for (int tile = 0; tile < ntiles; ++tile)
       for (int c = 0; c < p->nchans; ++c) {
         const int2 w = hw[static_cast<size_t>(tile) * p->nchans + c];
-        const int mis = window_mis(c, pitch, w.x, align);
-        const int64_t start = static_cast<int64_t>(c) * pitch + w.x - mis;
+        const int mis = window_mis(c, pitch_mod, w.x, align);
+        // from the row's start rounded down to align: c*pitch mod align, then lo - mis
+        const int64_t start = (static_cast<int64_t>(c) * pitch_mod) % align + w.x - mis;
         // bytes the tile's reads reach: its samples, the delay spread, the
         // start alignment and the halo lane's neighbour word
         const int64_t bytes = es * (static_cast<int64_t>(w.y) - w.x + mis + samples) + 8;

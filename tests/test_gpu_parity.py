@@ -149,6 +149,48 @@ def test_edge_shapes(dd, nchans, ndm, nsamp):
         assert np.array_equal(run(pu, xu, nsamp, variant=v).astype(np.int64), wantu)
 
 
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_staged_input_beyond_4gib(dd, dtype):
+    """A plan whose staged input is larger than 2^32 bytes (the tile kernels
+    address each row from its own base) on 1024 channels of a low band, with
+    trials dense enough for the tiles: a tiled variant and the direct kernel
+    against the oracle on sampled trials, every output sample."""
+    import torch
+    nchans, nsamp = 1024, 5000
+    band = wl.Band(nchans, 150.0, 0.09, 327.68e-6)
+    dms = (700.0 if dtype == "u8" else 360.0) + 0.1 * np.arange(64)
+    sh, m = oracle.shift_table(nchans, band.f_top, band.df, band.tsamp, dms)
+    staged = 2 if dtype == "u8" else 4
+    assert nchans * (nsamp + m) * staged > 2 ** 32
+    plan = dd.Plan(nchans, band.f_top, band.df, band.tsamp, dms, dtype)
+    assert plan.max_shift == m
+    print("staged input %.2f GB, max_shift %d" % (nchans * (nsamp + m) * staged / 1e9, m), flush=True)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    if dtype == "u8":
+        xin = torch.randint(0, 256, (nchans, nsamp + m), generator=g, device="cuda", dtype=torch.uint8)
+    else:
+        xin = torch.randn((nchans, nsamp + m), generator=g, device="cuda")
+    x = xin.cpu().numpy()
+    rows = np.array([0, 1, 7, 8, 31, 32, 63])
+    want = oracle.dedisperse(x, sh, nsamp, rows=rows)
+    scale = None if dtype == "u8" else abs_sum(x, sh, nsamp, rows=rows)
+    odt = torch.int32 if dtype == "u8" else torch.float32
+    for v in (1, 0):
+        plan.variant = v
+        out = torch.full((64, nsamp), -7, dtype=odt, device="cuda")
+        plan.execute(xin, out, nsamp, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()[rows]
+        if dtype == "u8":
+            assert np.array_equal(got.astype(np.int64), want), "variant %d" % v
+        else:
+            check_float(got, want, scale)
+        del out
+    del xin
+    torch.cuda.empty_cache()
+
+
 def test_unsorted_dm_list(dd):
     b = wl.SMALL
     dms = np.random.default_rng(3).permutation(wl.dm_grid(50, 0.2))
