@@ -405,6 +405,69 @@ def run_served(args) -> dict:
     }
 
 
+def run_fig4(args) -> dict:
+    """Both timing sweeps of the paper's Figure 4 on the stand-in band: as many
+    trials as channels, equally spaced up to a maximum DM (the library's grid
+    planner); (a) 256-4096 channels at a maximum DM of 200, (b) 2000 channels
+    with the maximum DM from 25 to 800.  Each point: tuned variant, median
+    kernel time over --steps launches (HIP events on the launch stream), and
+    that time as a percentage of the data's duration (the paper's axis)."""
+    import torch
+
+    from paper_1111_6399_amd import dedisp as dd
+    from paper_1111_6399_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    nsamp = 65536
+    points = []
+    for sweep, nchans, dm_max in wl.fig4_points():
+        band = wl.fig4_band(nchans)
+        plan = dd.Plan(nchans, band.f_top, band.df, band.tsamp, dd.dedisp_dm_grid(dm_max, nchans), "f32")
+        m = plan.max_shift
+        in_bytes, out_bytes, _ = dd.dedisp_plan_footprint(plan.handle, nsamp)
+        g = torch.Generator(device=dev)
+        g.manual_seed(100000 * nchans + int(dm_max))
+        x = torch.randn((nchans, nsamp + m), generator=g, device=dev)
+        out = torch.empty((nchans, nsamp), dtype=torch.float32, device=dev)
+        stream = torch.cuda.current_stream()
+        if args.variant >= 0:
+            plan.variant = args.variant
+        else:
+            dd.dedisp_autotune(plan.handle, nsamp)
+        for _ in range(max(1, args.warmup)):
+            plan.execute(x, out, nsamp, stream)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        ev[0].record(stream)
+        for i in range(args.steps):
+            plan.execute(x, out, nsamp, stream)
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.median([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]))
+        adds = float(nchans) * nchans * nsamp
+        pt = {"sweep": sweep, "nchans": nchans, "ndm": nchans, "dm_max": dm_max, "max_shift": m,
+              "input_gb": in_bytes / 1e9, "output_gb": out_bytes / 1e9, "variant": plan.variant,
+              "kernel_ms": ms, "adds_per_s": adds / (ms * 1e-3),
+              "pct_realtime": 100.0 * ms * 1e-3 / (nsamp * band.tsamp)}
+        points.append(pt)
+        log("fig4 %-8s nchans=ndm %4d  max DM %5.0f  max_shift %8d  input %6.2f GB  variant %2d  %8.3f ms  "
+            "%.3g adds/s  %.3f %% of real time" % (sweep, nchans, dm_max, m, in_bytes / 1e9, plan.variant, ms,
+                                                 adds / (ms * 1e-3), pt["pct_realtime"]))
+        del x, out
+        torch.cuda.empty_cache()
+    ref = [p for p in points if p["sweep"] == "channels" and p["nchans"] == 2048][0]
+    achieved = ref["adds_per_s"] / 1e12
+    return {
+        "metric": METRIC, "value": ref["adds_per_s"], "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ref["kernel_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "fig4-sweeps", "reference_point": "2048 channels = trials, max DM 200",
+                   "nsamp": nsamp, "band": "150 MHz top, 96.875 MHz wide, 327.68 us"},
+        "rtf": 100.0 / ref["pct_realtime"], "sweeps": points,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TADDS, "unit": "Tadd/s",
+                     "frac": achieved / ALU_PEAK_TADDS, "traffic": None},
+    }
+
+
 def roofline(w, adds, alg_bytes, kernel_ms, variant) -> dict:
     """Achieved add rate of the timed launch (HIP events on its stream) against
     the ALU add peak, with the LDS-read ceiling the accumulation also meets
@@ -444,8 +507,8 @@ def main() -> int:
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         return 2
 
-    if args.workload in ("batch-32", "served-meerkat"):
-        res = run_batch(args) if args.workload == "batch-32" else run_served(args)
+    if args.workload in ("batch-32", "served-meerkat", "fig4"):
+        res = {"batch-32": run_batch, "served-meerkat": run_served, "fig4": run_fig4}[args.workload](args)
         print(json.dumps(res), flush=True)
         return 0 if res.get("parity_spot_check", True) else 1
 

@@ -107,6 +107,31 @@ int dedisp_plan_shift_table(dedisp_plan plan, int32_t *host_out);
 int dedisp_plan_dims(dedisp_plan plan, int *nchans, int *ndm, int *in_dtype);
 
 /*
+ * Trial DMs equally spaced from 0 to dm_max inclusive, the grid of the
+ * paper's timing comparisons (section "Comparisons of GPU and CPU
+ * algorithms", Figure 4: as many equally spaced trials as channels, up to a
+ * maximum DM): dm_out[d] = dm_max * ((double)d / (ndm - 1)) in binary64 (the
+ * quotient first, so the last trial is dm_max exactly), d = 0 .. ndm-1;
+ * ndm = 1 gives {0}.
+ *   dm_max   finite, >= 0
+ *   ndm      >= 1
+ *   dm_out   host array of ndm doubles
+ * DEDISP_ERR_INVALID_ARG otherwise; nothing is written then.
+ */
+int dedisp_dm_grid(double dm_max, int ndm, double *dm_out);
+
+/*
+ * Device memory one dedisp_execute of a plan touches for nsamp >= 0 output
+ * samples: in_bytes = nchans*(nsamp + max_shift) samples of the input type;
+ * out_bytes = ndm*nsamp*4; staged_bytes = the widened copy a tiled launch of
+ * 8-bit or half input works from (16-bit or float samples, padded with zeros
+ * to a multiple of 8 samples, allocated stream-ordered by the launch), 0 for
+ * float input.  Any output pointer may be NULL.
+ */
+int dedisp_plan_footprint(dedisp_plan plan, int64_t nsamp, uint64_t *in_bytes, uint64_t *out_bytes,
+                          uint64_t *staged_bytes);
+
+/*
  * Kernel variants.  Variant 0 is the direct kernel (one lane per output
  * sample); variants 1..n-1 are LDS-tiled kernels of different tile shapes.
  * All variants produce identical results.  dedisp_variant_count returns the

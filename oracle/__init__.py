@@ -21,6 +21,9 @@ Functions and the passages they follow:
 * :func:`stream_reference` -- the same sum over a stream cut into blocks, with a
   zero history before the first block (the paper does not describe block
   buffering; this is the reading the streaming tests use).
+* :func:`dm_grid` -- trial DMs equally spaced from 0 up to a maximum DM, the
+  grid of the timing comparisons (section "Comparisons of GPU and CPU
+  algorithms", Figure 4: as many trials as channels).
 
 Every function here is pinned by ``tests/test_oracle_pins.py`` against results
 the mathematics fixes (exact rational arithmetic, closed forms, invariants, an
@@ -108,6 +111,19 @@ def shift_table(nchans: int, f_top: float, df: float, tsamp: float, dm_list) -> 
     if m < 0:
         raise ValueError("a delay does not fit in int32")
     return out, int(m)
+
+
+def dm_grid(dm_max: float, ndm: int) -> np.ndarray:
+    """Trial DMs equally spaced over [0, dm_max]: ``dm_max * (d / (ndm - 1))``
+    in binary64 for ``d = 0 .. ndm-1`` (the quotient first, so the last trial is
+    ``dm_max`` itself); one trial is ``[0]``.  Section "Comparisons of GPU and
+    CPU algorithms" (Figure 4 holds the maximum DM and spaces the trials
+    equally)."""
+    if ndm < 1 or not np.isfinite(dm_max) or dm_max < 0:
+        raise ValueError("ndm >= 1 and a finite dm_max >= 0 are required")
+    if ndm == 1:
+        return np.zeros(1)
+    return float(dm_max) * (np.arange(ndm, dtype=np.float64) / float(ndm - 1))
 
 
 def dedisperse(data: np.ndarray, shift: np.ndarray, nsamp: int, rows=None,

@@ -96,6 +96,31 @@ extern "C" int dedisp_plan_dims(dedisp_plan p, int* nchans, int* ndm, int* in_dt
   return DEDISP_OK;
 }
 
+extern "C" int dedisp_dm_grid(double dm_max, int ndm, double* dm_out) {
+  if (dm_out == nullptr || ndm < 1 || !std::isfinite(dm_max) || dm_max < 0.0) return DEDISP_ERR_INVALID_ARG;
+  if (ndm == 1) {
+    dm_out[0] = 0.0;
+    return DEDISP_OK;
+  }
+  const double den = static_cast<double>(ndm - 1);
+  for (int d = 0; d < ndm; ++d) dm_out[d] = dm_max * (static_cast<double>(d) / den);
+  return DEDISP_OK;
+}
+
+extern "C" int dedisp_plan_footprint(dedisp_plan p, int64_t nsamp, uint64_t* in_bytes, uint64_t* out_bytes,
+                                     uint64_t* staged_bytes) {
+  if (p == nullptr || nsamp < 0 || nsamp > static_cast<int64_t>(INT32_MAX) - p->max_shift)
+    return DEDISP_ERR_INVALID_ARG;
+  const uint64_t total = static_cast<uint64_t>(p->nchans) * static_cast<uint64_t>(nsamp + p->max_shift);
+  if (in_bytes) *in_bytes = total * dedisp::dtype_size(p->dtype);
+  if (out_bytes) *out_bytes = static_cast<uint64_t>(p->ndm) * static_cast<uint64_t>(nsamp) * 4u;
+  if (staged_bytes)
+    *staged_bytes = p->dtype == DEDISP_F32 ? 0u
+                                           : static_cast<uint64_t>(dedisp::widened_samples(static_cast<int64_t>(total))) *
+                                                 static_cast<uint64_t>(dedisp::staged_size(p->dtype));
+  return DEDISP_OK;
+}
+
 extern "C" int dedisp_plan_set_variant(dedisp_plan p, int variant) {
   if (p == nullptr || variant < 0 || variant >= dedisp::variant_count()) return DEDISP_ERR_INVALID_ARG;
   if (variant > 0 && !dedisp::variant_fits(p, variant)) return DEDISP_ERR_INVALID_ARG;

@@ -47,6 +47,8 @@ _SIGS = {
     "dedisp_plan_max_shift": (_i, [_p, ctypes.POINTER(ctypes.c_int32)]),
     "dedisp_plan_shift_table": (_i, [_p, ctypes.POINTER(ctypes.c_int32)]),
     "dedisp_plan_dims": (_i, [_p, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+    "dedisp_dm_grid": (_i, [_d, _i, ctypes.POINTER(_d)]),
+    "dedisp_plan_footprint": (_i, [_p, _i64, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
     "dedisp_variant_count": (_i, []),
     "dedisp_variant_describe": (_i, [_i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "dedisp_plan_set_variant": (_i, [_p, _i]),
@@ -124,6 +126,19 @@ def dedisp_plan_dims(plan: int):
     n, d, t = _i(), _i(), _i()
     _check(lib.dedisp_plan_dims(plan, ctypes.byref(n), ctypes.byref(d), ctypes.byref(t)), "dedisp_plan_dims")
     return n.value, d.value, t.value
+
+
+def dedisp_dm_grid(dm_max: float, ndm: int) -> np.ndarray:
+    out = np.empty(max(int(ndm), 1), dtype=np.float64)
+    _check(lib.dedisp_dm_grid(float(dm_max), int(ndm), out.ctypes.data_as(ctypes.POINTER(_d))), "dedisp_dm_grid")
+    return out
+
+
+def dedisp_plan_footprint(plan: int, nsamp: int):
+    a, b, c = _u64(), _u64(), _u64()
+    _check(lib.dedisp_plan_footprint(plan, int(nsamp), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+           "dedisp_plan_footprint")
+    return a.value, b.value, c.value
 
 
 def dedisp_plan_shift_table(plan: int) -> np.ndarray:

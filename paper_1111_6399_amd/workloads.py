@@ -87,6 +87,29 @@ def lofar(dtype: str = "f32", nsamp: int = 65536, ndm: int = 2048, seed: int = 2
     return Workload("lofar-%s" % dtype, LOFAR, dm_grid(ndm, 0.1), nsamp, dtype, seed, pulses)
 
 
+# Timing sweeps in the manner of the paper's Figure 4 (its band, sampling
+# interval and data length are not stated): the LOFAR-shaped band (150 MHz
+# top, 496 x 0.1953125 = 96.875 MHz wide, 327.68 us) cut into nchans
+# channels, as many trials as channels spaced equally up to a maximum DM,
+# 65536 output samples (21.5 s of data), float32 N(0,1) noise drawn on the
+# device.
+FIG4_BANDWIDTH = 496 * 0.1953125
+FIG4_CHANNELS = (256, 512, 1024, 2048, 4096)  # at a maximum DM of 200
+FIG4_DM_MAX = (25.0, 50.0, 100.0, 200.0, 400.0, 800.0)  # at 2000 channels and trials
+
+
+def fig4_band(nchans: int) -> Band:
+    """The LOFAR-shaped band cut into ``nchans`` channels."""
+    return Band(nchans, 150.0, FIG4_BANDWIDTH / nchans, 327.68e-6)
+
+
+def fig4_points():
+    """(sweep, nchans, maximum DM) of every point of both sweeps."""
+    pts = [("channels", n, 200.0) for n in FIG4_CHANNELS]
+    pts += [("max_dm", 2000, m) for m in FIG4_DM_MAX]
+    return pts
+
+
 def meerkat_block(nsamp: int = 32768, ndm: int = 4096, step: float = 0.5) -> Workload:
     """MeerKAT L-band-shaped block: 4096 channels from 1712 MHz, df 0.104492,
     tsamp 64 us, trials 0-2047.5 in steps of 0.5, uint8 samples."""

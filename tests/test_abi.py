@@ -162,3 +162,34 @@ def test_batch_create_checks(dd):
     with pytest.raises(dd.DedispError):
         dd.dedisp_batch_set_variant(b, 0)
     dd.dedisp_batch_destroy(b)
+
+
+@pytest.mark.parametrize("dm_max,ndm", [(200.0, 2000), (0.1, 4), (1000.0, 3), (0.0, 7), (25.0, 1)])
+def test_dm_grid_matches_oracle(dd, dm_max, ndm):
+    assert np.array_equal(dd.dedisp_dm_grid(dm_max, ndm).view(np.uint64), oracle.dm_grid(dm_max, ndm).view(np.uint64))
+
+
+def test_dm_grid_rejects(dd):
+    out = np.full(4, -1.0)
+    for bad in [(-1.0, 4), (float("nan"), 4), (float("inf"), 4), (1.0, 0), (1.0, -3)]:
+        assert dd.lib.dedisp_dm_grid(bad[0], bad[1], out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == \
+            dd.DEDISP_ERR_INVALID_ARG
+    assert np.all(out == -1.0)
+    assert dd.lib.dedisp_dm_grid(1.0, 4, None) == dd.DEDISP_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("dtype,es,staged", [("u8", 1, 2), ("f16", 2, 4), ("f32", 4, 0)])
+def test_plan_footprint(dd, dtype, es, staged):
+    band = wl.LOFAR
+    dms = oracle.dm_grid(200.0, 64)
+    sh, m = oracle.shift_table(band.nchans, band.f_top, band.df, band.tsamp, dms)
+    plan = dd.Plan(band.nchans, band.f_top, band.df, band.tsamp, dms, dtype)
+    for nsamp in (0, 1, 4097):
+        total = band.nchans * (nsamp + m)
+        i, o, s = dd.dedisp_plan_footprint(plan.handle, nsamp)
+        assert i == total * es
+        assert o == 64 * nsamp * 4
+        assert s == (0 if staged == 0 else (total + 7) // 8 * 8 * staged)
+    with pytest.raises(dd.DedispError):
+        dd.dedisp_plan_footprint(plan.handle, -1)
+    assert dd.lib.dedisp_plan_footprint(None, 10, None, None, None) == dd.DEDISP_ERR_INVALID_ARG

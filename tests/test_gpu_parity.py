@@ -191,6 +191,51 @@ def test_staged_input_beyond_4gib(dd, dtype):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("nchans,dm_max,dtype,nsamp,rows", [
+    (256, 200.0, "f32", 2500, None),
+    (2000, 100.0, "f32", 1200, [0, 1, 7, 8, 999, 1000, 1998, 1999]),
+    (2000, 400.0, "u8", 1200, [0, 1, 7, 8, 999, 1000, 1998, 1999]),
+])
+def test_fig4_sweep_shapes(dd, nchans, dm_max, dtype, nsamp, rows):
+    """Points of the Figure 4 sweeps (as many trials as channels, equally spaced
+    up to a maximum DM, on the stand-in band) with the trials from the
+    library's grid planner, against the oracle's own grid and delay table."""
+    import torch
+    band = wl.fig4_band(nchans)
+    dms = dd.dedisp_dm_grid(dm_max, nchans)
+    assert np.array_equal(dms, oracle.dm_grid(dm_max, nchans))
+    sh, m = oracle.shift_table(nchans, band.f_top, band.df, band.tsamp, oracle.dm_grid(dm_max, nchans))
+    plan = dd.Plan(nchans, band.f_top, band.df, band.tsamp, dms, dtype)
+    assert plan.max_shift == m
+    # 2000 channels and trials fit a tile; at 256 the trials are too far apart
+    # (an 8-trial tile would span ~24k samples) and the direct kernel runs
+    assert (plan.variant >= 1) == (nchans == 2000)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(nchans + int(dm_max))
+    if dtype == "u8":
+        xin = torch.randint(0, 256, (nchans, nsamp + m), generator=g, device="cuda", dtype=torch.uint8)
+    else:
+        xin = torch.randn((nchans, nsamp + m), generator=g, device="cuda")
+    x = xin.cpu().numpy()
+    rows = np.arange(nchans) if rows is None else np.array(rows)
+    want = oracle.dedisperse(x, sh, nsamp, rows=rows)
+    scale = None if dtype == "u8" else abs_sum(x, sh, nsamp, rows=rows)
+    odt = torch.int32 if dtype == "u8" else torch.float32
+    for v in sorted({plan.variant, 0}) if nchans <= 256 else [plan.variant]:
+        plan.variant = v
+        out = torch.full((nchans, nsamp), -7, dtype=odt, device="cuda")
+        plan.execute(xin, out, nsamp, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()[rows]
+        if dtype == "u8":
+            assert np.array_equal(got.astype(np.int64), want), "variant %d" % v
+        else:
+            check_float(got, want, scale)
+        del out
+    del xin
+    torch.cuda.empty_cache()
+
+
 def test_unsorted_dm_list(dd):
     b = wl.SMALL
     dms = np.random.default_rng(3).permutation(wl.dm_grid(50, 0.2))

@@ -316,3 +316,25 @@ def test_rejects_short_rows_and_bad_ranges():
         oracle.dedisperse(x, sh, 16, t_begin=10, t_count=10)
     with pytest.raises(ValueError):
         oracle.dedisperse(x, sh, 16, rows=[3])
+
+
+@pytest.mark.parametrize("dm_max,ndm", [(200.0, 2000), (0.1, 4), (1000.0, 3), (0.0, 7), (123.456, 496)])
+def test_dm_grid_equal_spacing(dm_max, ndm):
+    """The trials run from 0 to the maximum DM exactly, and each lies within two
+    roundings (the quotient, then the product) of the exact rational value
+    d*dm_max/(ndm-1), i.e. equally spaced; a grid spaced by dm_max/ndm, or
+    shifted by one trial, misses that by orders of magnitude."""
+    g = oracle.dm_grid(dm_max, ndm)
+    assert g.shape == (ndm,) and g.dtype == np.float64
+    assert g[0] == 0.0 and g[-1] == dm_max
+    assert np.all(np.diff(g) >= 0)
+    for d in range(ndm):
+        exact = Fraction(dm_max) * Fraction(d, ndm - 1)
+        assert abs(Fraction(float(g[d])) - exact) <= 2 * Fraction(np.spacing(max(float(g[d]), 1e-300)))
+
+
+def test_dm_grid_single_trial_and_rejects():
+    assert oracle.dm_grid(200.0, 1).tolist() == [0.0]
+    for bad in [(-1.0, 5), (float("nan"), 5), (float("inf"), 5), (10.0, 0)]:
+        with pytest.raises(ValueError):
+            oracle.dm_grid(*bad)
