@@ -169,6 +169,49 @@ int dedisp_autotune(dedisp_plan plan, int64_t nsamp, int *best_variant, double *
  */
 int dedisp_execute(dedisp_plan plan, const void *in_dev, void *out_dev, int64_t nsamp, void *stream);
 
+/* ------------------------------------------------------------- detection -- */
+
+/* One detection: trial index, boxcar width in samples, start time of the
+ * boxcar in output samples, and its S/N. */
+typedef struct {
+    int32_t dm_index;
+    int32_t width;
+    int32_t time;
+    float snr;
+} dedisp_candidate;
+
+/*
+ * Detection on a de-dispersed block, the step after the search (section
+ * "Introduction": the pipeline ends in detection; Figure 3: the recovered
+ * pulse stands out at its trial DM).  For every trial d of the plan, over its
+ * nsamp output samples x_d:
+ *   mean_d, std_d       mean and population standard deviation, binary64
+ *   S/N_{d,w}(t)        (sum_{i<w} x_d[t+i] - w*mean_d) / (std_d*sqrt(w)) for
+ *                       w = 1, 2, 4, .. 2^(nwidths-1) and every t with
+ *                       t + w <= nsamp (0 where std_d = 0)
+ *   best_{d,w}          the largest S/N_{d,w}(t) and the earliest t reaching it;
+ *                       -inf and -1 when w > nsamp
+ * and every (d, w) whose best S/N is >= threshold is a candidate.
+ *   out_dev        device pointer to the block, [ndm][nsamp] int32 (U8 plans)
+ *                  or float32, 4-byte aligned; read only
+ *   nsamp          1 .. INT32_MAX
+ *   nwidths        1 .. 12
+ *   threshold      finite
+ *   stats_dev      device [ndm][2] doubles (mean, std), or NULL
+ *   best_snr_dev   device [ndm][nwidths] doubles
+ *   best_t_dev     device [ndm][nwidths] int32
+ *   cand_dev       device array of cand_capacity candidates (order unspecified),
+ *                  or NULL for none; cand_count_dev (device uint32) then
+ *                  receives the number of candidates, which may exceed the
+ *                  capacity (only the first cand_capacity are written)
+ *   stream         hipStream_t or NULL
+ * Values are converted to binary64 before any arithmetic (exact for int32).
+ * Asynchronous; all device buffers are the caller's.
+ */
+int dedisp_detect(dedisp_plan plan, const void *out_dev, int64_t nsamp, int nwidths, double threshold,
+                  double *stats_dev, double *best_snr_dev, int32_t *best_t_dev, dedisp_candidate *cand_dev,
+                  int cand_capacity, uint32_t *cand_count_dev, void *stream);
+
 /* --------------------------------------------------------------- batches -- */
 
 /*

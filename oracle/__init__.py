@@ -24,6 +24,11 @@ Functions and the passages they follow:
 * :func:`dm_grid` -- trial DMs equally spaced from 0 up to a maximum DM, the
   grid of the timing comparisons (section "Comparisons of GPU and CPU
   algorithms", Figure 4: as many trials as channels).
+* :func:`detect` -- the detection step after the search (section
+  "Introduction": the pipeline ends in detection; Figure 3: the recovered pulse
+  at its trial DM): per trial mean and standard deviation, boxcar S/N for
+  widths 1, 2, 4, ..., the best (S/N, time) per width, the candidates above a
+  threshold.  The paper gives no formula; this is the reading stated there.
 
 Every function here is pinned by ``tests/test_oracle_pins.py`` against results
 the mathematics fixes (exact rational arithmetic, closed forms, invariants, an
@@ -124,6 +129,39 @@ def dm_grid(dm_max: float, ndm: int) -> np.ndarray:
     if ndm == 1:
         return np.zeros(1)
     return float(dm_max) * (np.arange(ndm, dtype=np.float64) / float(ndm - 1))
+
+
+def detect(block: np.ndarray, nwidths: int, threshold: float):
+    """Detection on a de-dispersed block ``(ndm, n)`` (int or float), binary64.
+
+    Per trial ``d``: ``mean`` and population ``std`` of its ``n`` values; for
+    ``w = 2**k`` (``k < nwidths``) and every ``t`` with ``t + w <= n``:
+    ``snr = (sum(x[t:t+w]) - w*mean) / (std*sqrt(w))`` (0 where ``std == 0``);
+    ``best_snr[d][k]``, ``best_t[d][k]``: the largest ``snr`` and the earliest
+    ``t`` reaching it (``-inf``, ``-1`` when ``w > n``).  Candidates: the set of
+    ``(d, w)`` whose best S/N is ``>= threshold``.
+    Returns ``(stats (ndm, 2), best_snr, best_t, candidates)``.
+    """
+    x = np.asarray(block).astype(np.float64)
+    ndm, n = x.shape
+    mean = x.mean(axis=1)
+    std = np.sqrt(((x - mean[:, None]) ** 2).mean(axis=1))
+    best_snr = np.full((ndm, nwidths), -np.inf)
+    best_t = np.full((ndm, nwidths), -1, dtype=np.int64)
+    rows = np.arange(ndm)
+    for k in range(nwidths):
+        w = 1 << k
+        if w > n:
+            continue
+        box = np.lib.stride_tricks.sliding_window_view(x, w, axis=1).sum(axis=2)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            snr = (box - w * mean[:, None]) / (std[:, None] * np.sqrt(float(w)))
+        snr[std == 0.0] = 0.0
+        t = np.argmax(snr, axis=1)
+        best_t[:, k] = t
+        best_snr[:, k] = snr[rows, t]
+    cands = {(int(d), 1 << int(k)) for d, k in zip(*np.nonzero(best_snr >= threshold))}
+    return np.stack([mean, std], axis=1), best_snr, best_t, cands
 
 
 def dedisperse(data: np.ndarray, shift: np.ndarray, nsamp: int, rows=None,

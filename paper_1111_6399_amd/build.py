@@ -30,6 +30,7 @@ SOURCES = [
     ("autotune.cpp", "hip"),
     ("batch.cpp", "hip"),
     ("server.cpp", "hip"),
+    ("detect.hip", "hip"),
 ]
 
 

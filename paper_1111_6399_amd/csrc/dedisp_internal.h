@@ -24,6 +24,8 @@ constexpr int kGeoPad = 16;
 // Zero rows after the last channel of the device delay table (covers the
 // channels a kernel reads ahead past the last one).
 constexpr int kShiftPadRows = 16;
+// Boxcar widths the detection kernel supports (1 .. 2^11 samples).
+constexpr int kMaxDetectWidths = 12;
 
 
 inline size_t dtype_size(int dtype) { return dtype == DEDISP_U8 ? 1 : dtype == DEDISP_F16 ? 2 : 4; }
@@ -169,6 +171,10 @@ int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, T
 int prepare(dedisp_plan p, int v, int64_t nsamp);
 // Allow a kernel more than 64 KiB of dynamic LDS (once per kernel and device).
 int allow_large_lds(const void* fn);
+// Detection on a de-dispersed block (detect.hip); arguments checked by the caller.
+size_t detect_lds_bytes(int nwidths);
+int detect(dedisp_plan p, const void* out, int64_t nsamp, int nwidths, double threshold, double* stats,
+           double* best_snr, int32_t* best_t, dedisp_candidate* cand, int cap, unsigned* count, hipStream_t s);
 // Persistent batch kernel of variant v >= 1, and the counter reset kernel.
 const void* batch_kernel(int v);
 const void* reset_kernel();

@@ -55,6 +55,7 @@ _SIGS = {
     "dedisp_plan_get_variant": (_i, [_p, ctypes.POINTER(_i)]),
     "dedisp_autotune": (_i, [_p, _i64, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
     "dedisp_execute": (_i, [_p, _p, _p, _i64, _p]),
+    "dedisp_detect": (_i, [_p, _p, _i64, _i, _d, _p, _p, _p, _p, _i, _p, _p]),
     "dedisp_batch_create": (_i, [_pp, ctypes.POINTER(_i64), _i, _pp]),
     "dedisp_batch_execute": (_i, [_p, _pp, _pp, _p]),
     "dedisp_batch_info": (_i, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i)]),
@@ -178,6 +179,19 @@ def dedisp_autotune(plan: int, nsamp: int):
 
 def dedisp_execute(plan: int, in_ptr: int, out_ptr: int, nsamp: int, stream=None) -> None:
     _check(lib.dedisp_execute(plan, in_ptr, out_ptr, int(nsamp), _stream(stream)), "dedisp_execute")
+
+
+# -------------------------------------------------------------- detection
+
+# Layout of dedisp_candidate (four 4-byte fields).
+CANDIDATE_DTYPE = np.dtype([("dm_index", np.int32), ("width", np.int32), ("time", np.int32), ("snr", np.float32)])
+
+
+def dedisp_detect(plan: int, out_ptr: int, nsamp: int, nwidths: int, threshold: float, stats_ptr, snr_ptr: int,
+                  t_ptr: int, cand_ptr, cand_capacity: int, count_ptr, stream=None) -> None:
+    """Device pointers as integers (``stats_ptr``, ``cand_ptr``, ``count_ptr`` may be None)."""
+    _check(lib.dedisp_detect(plan, out_ptr, int(nsamp), int(nwidths), float(threshold), stats_ptr, snr_ptr, t_ptr,
+                             cand_ptr, int(cand_capacity), count_ptr, _stream(stream)), "dedisp_detect")
 
 
 # ---------------------------------------------------------------- batches

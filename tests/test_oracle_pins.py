@@ -338,3 +338,76 @@ def test_dm_grid_single_trial_and_rejects():
     for bad in [(-1.0, 5), (float("nan"), 5), (float("inf"), 5), (10.0, 0)]:
         with pytest.raises(ValueError):
             oracle.dm_grid(*bad)
+
+
+# ------------------------------------------------------------------ detection
+
+def test_detect_single_spike_closed_form():
+    """Constant c with one spike of A at t1: std = A*sqrt(n-1)/n, the width-1
+    S/N at t1 is sqrt(n-1), a width-2 boxcar over the spike gives
+    (n-2)/sqrt(2(n-1)) at its earliest start t1-1, and every other boxcar is
+    below its width's best."""
+    n, c, A, t1 = 1000, 3.0, 40.0, 417
+    x = np.full((1, n), c)
+    x[0, t1] += A
+    stats, snr, t, _ = oracle.detect(x, 3, 1e9)
+    assert abs(stats[0, 0] - (c + A / n)) < 1e-12
+    assert abs(stats[0, 1] - A * np.sqrt(n - 1) / n) < 1e-12
+    assert abs(snr[0, 0] - np.sqrt(n - 1)) < 1e-9 and t[0, 0] == t1
+    assert abs(snr[0, 1] - (n - 2) / np.sqrt(2 * (n - 1))) < 1e-9 and t[0, 1] == t1 - 1
+    assert abs(snr[0, 2] - (n - 4) / np.sqrt(4 * (n - 1))) < 1e-9 and t[0, 2] == t1 - 3
+
+
+def test_detect_affine_invariance():
+    """S/N and times do not change under x -> a*x + b (a > 0): the mean is
+    subtracted and the result divided by the std of the same trial."""
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal((6, 3000))
+    x[2, 1500:1508] += 3.0
+    s0, b0, t0, _ = oracle.detect(x, 6, 5.0)
+    s1, b1, t1, _ = oracle.detect(7.5 * x - 123.0, 6, 5.0)
+    assert np.allclose(b0, b1, rtol=0, atol=1e-9)
+    assert np.array_equal(t0, t1)
+    assert np.allclose(s1[:, 0], 7.5 * s0[:, 0] - 123.0) and np.allclose(s1[:, 1], 7.5 * s0[:, 1])
+
+
+def test_detect_matched_width():
+    """A box of width 8 and height h on zeros: the S/N grows as sqrt(w) up to
+    w = 8 and falls after it, so the best width is 8, starting at the box."""
+    n, h, t1 = 4096, 5.0, 1000
+    x = np.zeros((1, n))
+    x[0, t1:t1 + 8] = h
+    _, snr, t, cands = oracle.detect(x, 7, 0.0)
+    assert int(np.argmax(snr[0])) == 3 and t[0, 3] == t1
+    assert np.all(np.diff(snr[0, :4]) > 0) and np.all(np.diff(snr[0, 3:]) < 0)
+    assert (0, 8) in cands
+
+
+def test_detect_brute_force_tiny():
+    """Pure-Python loops on tiny blocks, one sum per boxcar."""
+    rng = np.random.default_rng(9)
+    x = rng.integers(-5, 6, size=(3, 13)).astype(np.float64)
+    stats, snr, t, cands = oracle.detect(x, 4, 1.5)
+    for d in range(3):
+        row = [float(v) for v in x[d]]
+        n = len(row)
+        mean = sum(row) / n
+        std = (sum((v - mean) ** 2 for v in row) / n) ** 0.5
+        for k in range(4):
+            w = 1 << k
+            best, bt = -np.inf, -1
+            for s in range(n - w + 1):
+                v = (sum(row[s:s + w]) - w * mean) / (std * w ** 0.5)
+                if v > best:
+                    best, bt = v, s
+            assert abs(snr[d, k] - best) < 1e-12 and t[d, k] == bt
+            assert ((d, w) in cands) == (best >= 1.5)
+
+
+def test_detect_degenerate_rows():
+    """A constant trial has S/N 0 everywhere (earliest time 0); widths longer
+    than the block have no boxcar."""
+    x = np.vstack([np.full(5, 7.0), np.arange(5.0)])
+    stats, snr, t, _ = oracle.detect(x, 4, 0.5)
+    assert stats[0, 1] == 0.0 and np.all(snr[0, :3] == 0.0) and np.all(t[0, :3] == 0)
+    assert snr[0, 3] == -np.inf and t[0, 3] == -1 and snr[1, 3] == -np.inf and t[1, 3] == -1
