@@ -169,6 +169,48 @@ int dedisp_autotune(dedisp_plan plan, int64_t nsamp, int *best_variant, double *
  */
 int dedisp_execute(dedisp_plan plan, const void *in_dev, void *out_dev, int64_t nsamp, void *stream);
 
+/* ------------------------------------------------------------- ingestion -- */
+
+/* Fields of a sigproc filterbank header that the search uses. */
+typedef struct {
+    int32_t nchans, nbits, nifs, data_type, telescope_id, machine_id, nbeams, ibeam, nsamples;
+    int32_t dtype;         /* DEDISP_U8 for 8-bit samples, DEDISP_F32 for 32-bit, -1 otherwise */
+    double tsamp;          /* seconds */
+    double fch1, foff;     /* MHz: centre of the first channel, channel step (negative: descending) */
+    double tstart, refdm;
+    int64_t header_bytes;  /* offset of the first sample */
+    char source_name[80];  /* NUL-terminated, truncated */
+} dedisp_sigproc_header;
+
+/*
+ * Parse a sigproc filterbank header (the format of the paper's test data,
+ * section "Searching for radio transients": simulated with sigproc) from the
+ * first len bytes of a host buffer.  The header is a sequence of keywords,
+ * each a 32-bit little-endian length and that many characters, between
+ * HEADER_START and HEADER_END, each followed by a 32-bit integer, a binary64
+ * value or a length-prefixed string according to the keyword.  Keywords not
+ * listed above are skipped when their value type is known (telescope
+ * coordinates, beam flags, period, raw file name).  Unset fields are 0 (nifs
+ * 1).  DEDISP_ERR_INVALID_ARG for a truncated or malformed header, an unknown
+ * keyword, nchans < 1, tsamp <= 0, foff = 0, nifs < 1 or nbits not 8, 16 or
+ * 32; *out is written only on success.  Samples follow the header in time
+ * order, nifs x nchans per time step.
+ */
+int dedisp_sigproc_parse(const void *buf, size_t len, dedisp_sigproc_header *out);
+
+/*
+ * Corner turn: time-major samples in_dev[t][c] (nsamp x nchans, the sample
+ * order of a filterbank with nifs = 1) into channel rows,
+ * out_dev[row * out_pitch + t], row = c, or nchans - 1 - c with
+ * reverse_channels (a band stored with ascending frequency, foff > 0, becomes
+ * channel 0 = highest, as plans expect).  out_pitch >= nsamp samples; writing
+ * to a plan input's row offset (out_dev + max_shift, pitch nsamp + max_shift)
+ * appends a block behind a history.  dtype: DEDISP_U8, DEDISP_F16 or
+ * DEDISP_F32 (element size only).  Device pointers; asynchronous on stream.
+ */
+int dedisp_corner_turn(const void *in_dev, void *out_dev, int64_t nsamp, int nchans, int64_t out_pitch,
+                       int dtype, int reverse_channels, void *stream);
+
 /* ------------------------------------------------------------- detection -- */
 
 /* One detection: trial index, boxcar width in samples, start time of the

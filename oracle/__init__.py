@@ -24,6 +24,10 @@ Functions and the passages they follow:
 * :func:`dm_grid` -- trial DMs equally spaced from 0 up to a maximum DM, the
   grid of the timing comparisons (section "Comparisons of GPU and CPU
   algorithms", Figure 4: as many trials as channels).
+* :func:`sigproc_header`, :func:`corner_turn` -- ingestion of sigproc
+  filterbank data (the paper's test data were sigproc simulations, section
+  "Searching for radio transients"): the header's keywords and values, and the
+  time-major samples rearranged into one row per channel.
 * :func:`detect` -- the detection step after the search (section
   "Introduction": the pipeline ends in detection; Figure 3: the recovered pulse
   at its trial DM): per trial mean and standard deviation, boxcar S/N for
@@ -116,6 +120,63 @@ def shift_table(nchans: int, f_top: float, df: float, tsamp: float, dm_list) -> 
     if m < 0:
         raise ValueError("a delay does not fit in int32")
     return out, int(m)
+
+
+_SIGPROC_INT = {"telescope_id", "machine_id", "data_type", "nchans", "nbits", "nifs", "nbeams", "ibeam",
+                 "barycentric", "pulsarcentric", "nsamples"}
+_SIGPROC_DOUBLE = {"tsamp", "fch1", "foff", "tstart", "src_raj", "src_dej", "az_start", "za_start", "refdm",
+                   "period"}
+_SIGPROC_STRING = {"source_name", "rawdatafile"}
+
+
+def sigproc_header(buf: bytes) -> dict:
+    """Keywords and values of a sigproc filterbank header: length-prefixed
+    (32-bit little-endian) keyword strings between HEADER_START and
+    HEADER_END, each followed by a 32-bit integer, a binary64 value or a
+    length-prefixed string.  Adds ``header_bytes``, the offset of the first
+    sample.  Raises ValueError on a malformed header or unknown keyword."""
+    import struct
+
+    pos = 0
+
+    def string():
+        nonlocal pos
+        (n,) = struct.unpack_from("<i", buf, pos)
+        if not 0 < n <= 256 or pos + 4 + n > len(buf):
+            raise ValueError("bad string at %d" % pos)
+        v = bytes(buf[pos + 4:pos + 4 + n]).decode("latin-1")
+        pos += 4 + n
+        return v
+
+    try:
+        if string() != "HEADER_START":
+            raise ValueError("no HEADER_START")
+        out = {}
+        while True:
+            key = string()
+            if key == "HEADER_END":
+                break
+            if key in _SIGPROC_INT:
+                (out[key],) = struct.unpack_from("<i", buf, pos)
+                pos += 4
+            elif key in _SIGPROC_DOUBLE:
+                (out[key],) = struct.unpack_from("<d", buf, pos)
+                pos += 8
+            elif key in _SIGPROC_STRING:
+                out[key] = string()
+            else:
+                raise ValueError("unknown keyword %r" % key)
+    except struct.error as e:
+        raise ValueError("truncated header") from e
+    out["header_bytes"] = pos
+    return out
+
+
+def corner_turn(samples: np.ndarray, reverse_channels: bool = False) -> np.ndarray:
+    """Time-major ``samples[t][c]`` as channel rows ``out[c][t]``; with
+    ``reverse_channels`` input channel c becomes row ``nchans-1-c``."""
+    out = np.ascontiguousarray(np.asarray(samples).T)
+    return np.ascontiguousarray(out[::-1]) if reverse_channels else out
 
 
 def dm_grid(dm_max: float, ndm: int) -> np.ndarray:

@@ -31,6 +31,8 @@ SOURCES = [
     ("batch.cpp", "hip"),
     ("server.cpp", "hip"),
     ("detect.hip", "hip"),
+    ("ingest.hip", "hip"),
+    ("sigproc.cpp", "host"),
 ]
 
 

@@ -171,6 +171,9 @@ int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, T
 int prepare(dedisp_plan p, int v, int64_t nsamp);
 // Allow a kernel more than 64 KiB of dynamic LDS (once per kernel and device).
 int allow_large_lds(const void* fn);
+// Corner turn [t][c] -> rows [c][t] (ingest.hip); arguments checked by the caller.
+int corner_turn(const void* in, void* out, int64_t nsamp, int nchans, int64_t pitch, int dtype, int reverse,
+                hipStream_t s);
 // Detection on a de-dispersed block (detect.hip); arguments checked by the caller.
 size_t detect_lds_bytes(int nwidths);
 int detect(dedisp_plan p, const void* out, int64_t nsamp, int nwidths, double threshold, double* stats,

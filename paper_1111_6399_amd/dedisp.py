@@ -56,6 +56,8 @@ _SIGS = {
     "dedisp_autotune": (_i, [_p, _i64, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
     "dedisp_execute": (_i, [_p, _p, _p, _i64, _p]),
     "dedisp_detect": (_i, [_p, _p, _i64, _i, _d, _p, _p, _p, _p, _i, _p, _p]),
+    "dedisp_sigproc_parse": (_i, [_p, ctypes.c_size_t, _p]),
+    "dedisp_corner_turn": (_i, [_p, _p, _i64, _i, _i64, _i, _i, _p]),
     "dedisp_batch_create": (_i, [_pp, ctypes.POINTER(_i64), _i, _pp]),
     "dedisp_batch_execute": (_i, [_p, _pp, _pp, _p]),
     "dedisp_batch_info": (_i, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i)]),
@@ -179,6 +181,34 @@ def dedisp_autotune(plan: int, nsamp: int):
 
 def dedisp_execute(plan: int, in_ptr: int, out_ptr: int, nsamp: int, stream=None) -> None:
     _check(lib.dedisp_execute(plan, in_ptr, out_ptr, int(nsamp), _stream(stream)), "dedisp_execute")
+
+
+# -------------------------------------------------------------- ingestion
+
+# Layout of dedisp_sigproc_header (C struct with natural alignment).
+SIGPROC_HEADER_DTYPE = np.dtype([("nchans", np.int32), ("nbits", np.int32), ("nifs", np.int32),
+                                 ("data_type", np.int32), ("telescope_id", np.int32), ("machine_id", np.int32),
+                                 ("nbeams", np.int32), ("ibeam", np.int32), ("nsamples", np.int32),
+                                 ("dtype", np.int32), ("tsamp", np.float64), ("fch1", np.float64),
+                                 ("foff", np.float64), ("tstart", np.float64), ("refdm", np.float64),
+                                 ("header_bytes", np.int64), ("source_name", "S80")], align=True)
+
+
+def dedisp_sigproc_parse(buf: bytes) -> dict:
+    """Parse a sigproc header from the start of ``buf`` (bytes)."""
+    raw = np.frombuffer(bytes(buf), dtype=np.uint8)
+    h = np.zeros(1, dtype=SIGPROC_HEADER_DTYPE)
+    _check(lib.dedisp_sigproc_parse(raw.ctypes.data, raw.size, h.ctypes.data), "dedisp_sigproc_parse")
+    out = {k: h[0][k].item() for k in SIGPROC_HEADER_DTYPE.names}
+    out["source_name"] = h[0]["source_name"].decode("latin-1")
+    return out
+
+
+def dedisp_corner_turn(in_ptr: int, out_ptr: int, nsamp: int, nchans: int, out_pitch: int, in_dtype,
+                       reverse_channels: bool = False, stream=None) -> None:
+    dt = DTYPES[in_dtype] if isinstance(in_dtype, str) else int(in_dtype)
+    _check(lib.dedisp_corner_turn(in_ptr, out_ptr, int(nsamp), int(nchans), int(out_pitch), dt,
+                                  1 if reverse_channels else 0, _stream(stream)), "dedisp_corner_turn")
 
 
 # -------------------------------------------------------------- detection

@@ -193,3 +193,44 @@ def test_plan_footprint(dd, dtype, es, staged):
     with pytest.raises(dd.DedispError):
         dd.dedisp_plan_footprint(plan.handle, -1)
     assert dd.lib.dedisp_plan_footprint(None, 10, None, None, None) == dd.DEDISP_ERR_INVALID_ARG
+
+
+def _sigproc(fields):
+    from sigproc_util import SIGPROC_FIELDS, write_sigproc
+    return write_sigproc(fields), SIGPROC_FIELDS
+
+
+def test_sigproc_parse_matches_oracle(dd):
+    buf, fields = _sigproc({"nchans": 3})
+    buf, _ = _sigproc(fields)
+    for extra in (b"", bytes(100)):
+        got = dd.dedisp_sigproc_parse(buf + extra)
+        want = oracle.sigproc_header(buf + extra)
+        for k in ("nchans", "nbits", "nifs", "data_type", "telescope_id", "machine_id", "tsamp", "fch1", "foff",
+                  "tstart", "refdm", "source_name", "header_bytes"):
+            assert got[k] == want[k], k
+        assert got["dtype"] == dd.DEDISP_U8
+
+
+def test_sigproc_parse_rejects(dd):
+    good, _ = _sigproc({"nchans": 4, "nbits": 8, "tsamp": 1e-3, "foff": -1.0, "fch1": 100.0})
+    assert dd.dedisp_sigproc_parse(good)["dtype"] == dd.DEDISP_U8
+    f32, _ = _sigproc({"nchans": 4, "nbits": 32, "tsamp": 1e-3, "foff": 1.0, "fch1": 100.0})
+    assert dd.dedisp_sigproc_parse(f32)["dtype"] == dd.DEDISP_F32
+    bads = [good[:-3], good[4:], _sigproc({"nchans": 4, "nbits": 8, "tsamp": 1e-3, "foff": 0.0})[0],
+            _sigproc({"nchans": 0, "nbits": 8, "tsamp": 1e-3, "foff": 1.0})[0],
+            _sigproc({"nchans": 4, "nbits": 12, "tsamp": 1e-3, "foff": 1.0})[0],
+            good.replace(b"nchans", b"nchanz")]
+    for b in bads:
+        with pytest.raises(dd.DedispError):
+            dd.dedisp_sigproc_parse(b)
+    assert dd.lib.dedisp_sigproc_parse(None, 10, None) == dd.DEDISP_ERR_INVALID_ARG
+
+
+def test_corner_turn_argument_checks(dd):
+    f = dd.lib.dedisp_corner_turn
+    assert f(None, 16, 10, 4, 10, dd.DEDISP_U8, 0, None) == dd.DEDISP_ERR_INVALID_ARG
+    assert f(16, 16, 10, 4, 9, dd.DEDISP_U8, 0, None) == dd.DEDISP_ERR_INVALID_ARG  # pitch < nsamp
+    assert f(16, 16, 10, 0, 10, dd.DEDISP_U8, 0, None) == dd.DEDISP_ERR_INVALID_ARG
+    assert f(16, 16, 10, 4, 10, 7, 0, None) == dd.DEDISP_ERR_INVALID_ARG
+    assert f(16, 16, 0, 4, 10, dd.DEDISP_U8, 0, None) == dd.DEDISP_OK  # nothing to do, no device call

@@ -411,3 +411,36 @@ def test_detect_degenerate_rows():
     stats, snr, t, _ = oracle.detect(x, 4, 0.5)
     assert stats[0, 1] == 0.0 and np.all(snr[0, :3] == 0.0) and np.all(t[0, :3] == 0)
     assert snr[0, 3] == -np.inf and t[0, 3] == -1 and snr[1, 3] == -np.inf and t[1, 3] == -1
+
+
+# ------------------------------------------------------------------ ingestion
+
+from sigproc_util import SIGPROC_FIELDS, write_sigproc  # noqa: E402
+
+def test_sigproc_header_reads_every_field():
+    """A header written from the format's definition reads back field by
+    field, whatever the keyword order; the data offset is the header length."""
+    for order in (None, sorted(SIGPROC_FIELDS), list(reversed(list(SIGPROC_FIELDS)))):
+        buf = write_sigproc(SIGPROC_FIELDS, order)
+        h = oracle.sigproc_header(buf + bytes(range(16)))
+        for k, v in SIGPROC_FIELDS.items():
+            assert h[k] == v, k
+        assert h["header_bytes"] == len(buf)
+
+
+def test_sigproc_header_rejects():
+    good = write_sigproc({"nchans": 4, "nbits": 8, "tsamp": 1e-3, "foff": -1.0, "fch1": 100.0})
+    for bad in [good[:-3], good[4:], b"\x05\x00\x00\x00HELLO" + good[16:],
+                write_sigproc({"nchans": 4}).replace(b"nchans", b"nchanz")]:
+        with pytest.raises(ValueError):
+            oracle.sigproc_header(bad)
+
+
+def test_corner_turn_definition():
+    """Element (t, c) lands in row c (or nchans-1-c) at column t."""
+    x = np.arange(7 * 5).reshape(7, 5)
+    y = oracle.corner_turn(x)
+    r = oracle.corner_turn(x, True)
+    for t in range(7):
+        for c in range(5):
+            assert y[c, t] == x[t, c] and r[4 - c, t] == x[t, c]
