@@ -254,6 +254,23 @@ int dedisp_detect(dedisp_plan plan, const void *out_dev, int64_t nsamp, int nwid
                   double *stats_dev, double *best_snr_dev, int32_t *best_t_dev, dedisp_candidate *cand_dev,
                   int cand_capacity, uint32_t *cand_count_dev, void *stream);
 
+/* ------------------------------------------------------------------ host -- */
+
+/*
+ * The search on the host CPU, for timing against the GPU: the paper's second
+ * algorithm (section "Comparisons of GPU and CPU algorithms": a brute force
+ * written for the CPU's vector registers with cache-line reuse in mind), in
+ * tiles of 16 trials x 256 samples.  Same plan, layouts and results as
+ * dedisp_execute, with host pointers: float sums follow the GPU kernels' order
+ * (channels in blocks of 32), so float results are bit-identical to
+ * dedisp_execute's; 8-bit sums are exact.
+ *   nthreads   >= 0; 0 uses every hardware thread
+ *   isa_used   NULL, or receives 2 (AVX-512), 1 (AVX2) or 0 (plain C++)
+ * Synchronous.  dedisp_execute never calls it: there is no CPU fallback.
+ */
+int dedisp_execute_cpu(dedisp_plan plan, const void *in_host, void *out_host, int64_t nsamp, int nthreads,
+                       int *isa_used);
+
 /* --------------------------------------------------------------- batches -- */
 
 /*

@@ -33,6 +33,7 @@ SOURCES = [
     ("detect.hip", "hip"),
     ("ingest.hip", "hip"),
     ("sigproc.cpp", "host"),
+    ("cpu_kernel.cpp", "cxx"),
 ]
 
 
@@ -42,9 +43,11 @@ def _compile(src: str, kind: str) -> str:
     if kind == "host":
         cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall",
                "-c", path, "-o", obj]
+    elif kind == "cxx":  # host-only C++ that uses the HIP headers (no device pass)
+        cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__",
+               "-I" + os.path.join(ROCM, "include"), "-I" + CSRC, "-x", "c++", "-c", path, "-o", obj]
     else:
-        lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
-        cmd = [HIPCC] + HIP_FLAGS + lang + ["-c", path, "-o", obj]
+        cmd = [HIPCC] + HIP_FLAGS + ["-x", "hip", "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))

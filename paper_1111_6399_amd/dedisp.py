@@ -57,6 +57,7 @@ _SIGS = {
     "dedisp_execute": (_i, [_p, _p, _p, _i64, _p]),
     "dedisp_detect": (_i, [_p, _p, _i64, _i, _d, _p, _p, _p, _p, _i, _p, _p]),
     "dedisp_sigproc_parse": (_i, [_p, ctypes.c_size_t, _p]),
+    "dedisp_execute_cpu": (_i, [_p, _p, _p, _i64, _i, ctypes.POINTER(_i)]),
     "dedisp_corner_turn": (_i, [_p, _p, _i64, _i, _i64, _i, _i, _p]),
     "dedisp_batch_create": (_i, [_pp, ctypes.POINTER(_i64), _i, _pp]),
     "dedisp_batch_execute": (_i, [_p, _pp, _pp, _p]),
@@ -181,6 +182,16 @@ def dedisp_autotune(plan: int, nsamp: int):
 
 def dedisp_execute(plan: int, in_ptr: int, out_ptr: int, nsamp: int, stream=None) -> None:
     _check(lib.dedisp_execute(plan, in_ptr, out_ptr, int(nsamp), _stream(stream)), "dedisp_execute")
+
+
+# ------------------------------------------------------------------- host
+
+def dedisp_execute_cpu(plan: int, in_array, out_array, nsamp: int, nthreads: int = 0) -> int:
+    """Host arrays (numpy, C-contiguous); returns the vector ISA level used."""
+    isa = _i()
+    _check(lib.dedisp_execute_cpu(plan, in_array.ctypes.data, out_array.ctypes.data, int(nsamp), int(nthreads),
+                                  ctypes.byref(isa)), "dedisp_execute_cpu")
+    return isa.value
 
 
 # -------------------------------------------------------------- ingestion

@@ -234,3 +234,58 @@ def test_corner_turn_argument_checks(dd):
     assert f(16, 16, 10, 0, 10, dd.DEDISP_U8, 0, None) == dd.DEDISP_ERR_INVALID_ARG
     assert f(16, 16, 10, 4, 10, 7, 0, None) == dd.DEDISP_ERR_INVALID_ARG
     assert f(16, 16, 0, 4, 10, dd.DEDISP_U8, 0, None) == dd.DEDISP_OK  # nothing to do, no device call
+
+
+# ------------------------------------------------- vectorised host search --
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "u8"])
+@pytest.mark.parametrize("nchans,ndm,nsamp", [(1, 1, 1), (33, 17, 257), (70, 40, 1000), (496, 64, 3000)])
+def test_execute_cpu_matches_oracle(dd, dtype, nchans, ndm, nsamp):
+    """The host search (host code, no device): exact for 8-bit input, within
+    the float tolerance otherwise; full and ragged tiles of 16 trials x 256
+    samples, channel counts that are not multiples of 32."""
+    band = wl.Band(nchans, 150.0, 0.1953125, 327.68e-6)
+    dms = np.arange(ndm) * 0.37
+    sh, m = oracle.shift_table(nchans, band.f_top, band.df, band.tsamp, dms)
+    rng = np.random.default_rng([41, nchans, ndm])
+    if dtype == "u8":
+        x = rng.integers(0, 256, size=(nchans, nsamp + m)).astype(np.uint8)
+    else:
+        x = rng.standard_normal((nchans, nsamp + m)).astype(np.float32 if dtype == "f32" else np.float16)
+    plan = dd.Plan(nchans, band.f_top, band.df, band.tsamp, dms, dtype)
+    out = np.empty((ndm, nsamp), dtype=np.int32 if dtype == "u8" else np.float32)
+    for nt in (1, 3, 0):
+        out[:] = -7
+        isa = dd.dedisp_execute_cpu(plan.handle, x, out, nsamp, nt)
+        assert isa in (0, 1, 2)
+        want = oracle.dedisperse(x, sh, nsamp)
+        if dtype == "u8":
+            assert np.array_equal(out.astype(np.int64), want)
+        else:
+            scale = oracle.dedisperse(np.abs(x.astype(np.float32)), sh, nsamp)
+            assert np.all(np.abs(out - want) <= 1e-5 * scale)
+
+
+def test_execute_cpu_same_result_any_threads(dd):
+    """Float results do not depend on the thread count (fixed summation order)."""
+    w = wl.lofar("f32", nsamp=1500, ndm=100)
+    b = w.band
+    sh, m = oracle.shift_table(b.nchans, b.f_top, b.df, b.tsamp, w.dms)
+    x = wl.generate(w, sh, m)
+    plan = dd.Plan.for_workload(w)
+    outs = []
+    for nt in (1, 2, 7):
+        o = np.empty((w.ndm, w.nsamp), np.float32)
+        dd.dedisp_execute_cpu(plan.handle, x, o, w.nsamp, nt)
+        outs.append(o)
+    assert all(np.array_equal(o.view(np.uint32), outs[0].view(np.uint32)) for o in outs)
+
+
+def test_execute_cpu_argument_checks(dd):
+    plan = dd.Plan(4, 150.0, 0.5, 1e-3, [0.0, 1.0], "f32")
+    f = dd.lib.dedisp_execute_cpu
+    assert f(None, 16, 16, 10, 0, None) == dd.DEDISP_ERR_INVALID_ARG
+    assert f(plan.handle, None, 16, 10, 0, None) == dd.DEDISP_ERR_INVALID_ARG
+    assert f(plan.handle, 16, 16, -1, 0, None) == dd.DEDISP_ERR_INVALID_ARG
+    assert f(plan.handle, 16, 16, 10, -2, None) == dd.DEDISP_ERR_INVALID_ARG
+    assert f(plan.handle, None, None, 0, 0, None) == dd.DEDISP_OK  # nothing to do

@@ -268,3 +268,17 @@ def test_execute_rejects_bad_pointers(dd):
         dd.dedisp_execute(p.handle, 0, out.data_ptr(), 100)
     with pytest.raises(dd.DedispError):
         dd.dedisp_execute(p.handle, x.data_ptr(), out.data_ptr(), -1)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_host_search_bit_identical_to_device(dd, dtype):
+    """The vectorised host search sums in the GPU kernels' order: its float
+    results equal dedisp_execute's bit for bit (tiled and direct variants)."""
+    w = wl.lofar(dtype, nsamp=2600, ndm=300)
+    sh, m, x = make_case(w)
+    plan = dd.Plan.for_workload(w)
+    host = np.empty((w.ndm, w.nsamp), np.float32)
+    dd.dedisp_execute_cpu(plan.handle, x, host, w.nsamp, 0)
+    for v in sorted({0, plan.variant}):
+        got = run(plan, x, w.nsamp, variant=v)
+        assert np.array_equal(got.view(np.uint32), host.view(np.uint32)), "variant %d" % v
