@@ -47,7 +47,7 @@ def measured_traffic(workload_name: str, variant: int):
     FETCH_SIZE/WRITE_SIZE summary (scaled by a plain copy), or None when the
     kernel source or variant differs from the one the counters were taken on."""
     try:
-        rec = json.load(open(TRAFFIC_FILE)).get(workload_name)
+        rec = json.load(open(TRAFFIC_FILE)).get("%s/v%d" % (workload_name, variant))
     except (OSError, ValueError):
         return None
     if not rec or rec.get("kernel_sha256") != kernel_sha() or rec.get("variant") != variant:
