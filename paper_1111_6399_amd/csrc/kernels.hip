@@ -479,7 +479,8 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
   // inputs are padded to whole groups.)
   float tail[3] = {0.f, 0.f, 0.f};
   int c_tail = nchans;  // first channel whose window can reach them
-  if (!kPairs && a.ntail > 0) {
+  const bool has_tail = !kPairs && a.ntail > 0;  // the same for the whole launch
+  if (has_tail) {
     const float* inf = static_cast<const float*>(a.in);
 #pragma unroll
     for (int k = 0; k < 3; ++k)
@@ -596,7 +597,7 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
     const int c0 = s * CG;
     const uint32_t sbase = (s & 1) ? CG * slot_bytes : 0u;
     wait_vm<0>();  // this wave's loads of the stage (if it issued any) are in LDS
-    patch(c0 + grp, static_cast<uint32_t>(wcur), rcur, sbase + grp * slot_bytes);
+    if (has_tail) patch(c0 + grp, static_cast<uint32_t>(wcur), rcur, sbase + grp * slot_bytes);
     lds_barrier_asm();
     // the other stage's slots are free: issue this group's channel of the next stage
     issue(c0 + CG + grp, static_cast<uint32_t>(wnext), rnext, (sbase ^ (CG * slot_bytes)) + grp * slot_bytes);
