@@ -21,7 +21,8 @@ NP = {"u8": np.uint8, "f16": np.float16, "f32": np.float32}
 
 
 @pytest.mark.parametrize("dtype", ["u8", "f16", "f32"])
-@pytest.mark.parametrize("nsamp,nchans", [(1, 1), (64, 64), (65, 63), (1000, 100), (4097, 513)])
+@pytest.mark.parametrize("nsamp,nchans", [(1, 1), (64, 64), (65, 63), (1000, 100), (4097, 513), (5, 4), (300, 260),
+                                          (129, 1024)])
 @pytest.mark.parametrize("reverse", [False, True])
 def test_corner_turn_matches_oracle(dd, dtype, nsamp, nchans, reverse):
     import torch
@@ -39,6 +40,52 @@ def test_corner_turn_matches_oracle(dd, dtype, nsamp, nchans, reverse):
     want = oracle.corner_turn(x, reverse)
     assert np.array_equal(got[:nchans, :nsamp].view(np.uint8), want.view(np.uint8))
     assert np.array_equal(got[:, nsamp:], sentinel[:, nsamp:]) and np.array_equal(got[nchans], sentinel[nchans])
+
+
+@pytest.mark.parametrize("offset", [0, 1, 3, 8, 15])
+@pytest.mark.parametrize("nsamp,nchans,extra", [(300, 260, 37), (1, 4, 0), (17, 512, 3), (1000, 8, 16)])
+def test_corner_turn_u8_any_output_alignment(dd, offset, nsamp, nchans, extra):
+    """8-bit rows written at any byte alignment (the plan's input places a
+    block behind the history, max_shift samples into each row): every sample
+    lands once, nothing outside the rows is touched."""
+    import torch
+    rng = np.random.default_rng([33, offset, nsamp, nchans])
+    x = rng.integers(0, 256, size=(nsamp, nchans)).astype(np.uint8)
+    pitch = nsamp + extra
+    tin = torch.from_numpy(x).to("cuda")
+    size = offset + nchans * pitch + 64
+    sentinel = rng.integers(0, 256, size=size).astype(np.uint8)
+    tout = torch.from_numpy(sentinel.copy()).to("cuda")
+    for reverse in (False, True):
+        dd.dedisp_corner_turn(tin.data_ptr(), tout.data_ptr() + offset, nsamp, nchans, pitch, "u8", reverse,
+                              torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        got = tout.cpu().numpy()
+        rows = got[offset:offset + nchans * pitch].reshape(nchans, pitch)
+        assert np.array_equal(rows[:, :nsamp], oracle.corner_turn(x, reverse))
+        keep = np.ones(size, dtype=bool)
+        keep[offset:offset + nchans * pitch] = np.tile(np.arange(pitch) >= nsamp, nchans)
+        assert np.array_equal(got[keep], sentinel[keep])
+
+
+def test_corner_turn_meerkat_block(dd):
+    """The MeerKAT-shaped block of the pipeline (32768 samples x 4096 uint8
+    channels) into rows behind a history of max_shift samples, exactly."""
+    import torch
+    from paper_1111_6399_amd import workloads as wl
+    w = wl.meerkat_block()
+    nch, n = w.band.nchans, w.nsamp
+    m = dd.Plan.for_workload(w).max_shift
+    rng = np.random.default_rng(34)
+    x = rng.integers(0, 256, size=(n, nch)).astype(np.uint8)
+    tin = torch.from_numpy(x).to("cuda")
+    rows = torch.zeros((nch, n + m), dtype=torch.uint8, device="cuda")
+    dd.dedisp_corner_turn(tin.data_ptr(), rows.data_ptr() + m, n, nch, n + m, "u8", False,
+                          torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    got = rows.cpu().numpy()
+    assert not got[:, :m].any()
+    assert np.array_equal(got[:, m:], x.T)
 
 
 @pytest.mark.parametrize("foff", [-0.390625, 0.390625])
