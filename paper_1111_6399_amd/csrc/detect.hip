@@ -8,7 +8,8 @@
 //      (per-thread runs, then a scan over the workgroup), so every boxcar is
 //      one difference, b_w(t) = P[t + w] - P[t]; the S/N of every complete
 //      boxcar (b_w(t) - w*mean) / (std*sqrt(w)) and the best (S/N, time) per
-//      width, the earliest time on ties;
+//      width, the earliest time on ties (integer rows: the best sum, whose
+//      S/N is the best S/N at the same time, see boxcars());
 //   3. (trial, width) pairs whose best S/N reaches the threshold appended to
 //      a candidate list through one atomic counter.
 // Values are converted to binary64 on load, so the prefix sums of the int32
@@ -19,6 +20,7 @@
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "dedisp_internal.h"
 
@@ -28,6 +30,12 @@ namespace {
 constexpr int kDetThreads = 256;
 constexpr int kDetChunk = 4096;  // boxcar start times per LDS chunk
 constexpr int kUnroll = 8;       // global loads in flight per thread
+
+// The S/N of a boxcar of width 2^k with sum b is (b - snr_base) * snr_scale.
+__device__ __forceinline__ double snr_base(int k, double mean) { return static_cast<double>(1 << k) * mean; }
+__device__ __forceinline__ double snr_scale(int k, double sd) {
+  return sd > 0.0 ? 1.0 / (sd * sqrt(static_cast<double>(1 << k))) : 0.0;
+}
 
 // Sum over the workgroup (every thread gets the result).
 __device__ double block_sum(double v, double* red) {
@@ -43,14 +51,47 @@ __device__ double block_sum(double v, double* red) {
   return r;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kDetThreads) void detect_rows(const T* __restrict__ out, int64_t nsamp, int nw,
+// Every complete boxcar starting at i < ni of a chunk held as prefix sums
+// P[0..L] from time t0, folded into the best (value, time) per width.  All
+// NW + 1 sums a start needs are read before any is used; kGuard: the chunk
+// ends at the row's end, so the widest boxcars of its last starts are
+// incomplete (and P is read at L instead).  kSums: the value is the boxcar
+// sum itself.  That is for integer rows, whose sums are exact integers below
+// 2^53: there (b - base) * inv, with inv > 0, is strictly increasing in b
+// (distinct integers stay distinct through both roundings), and all S/N are 0
+// when inv is 0 (a constant row, all sums equal), so the largest sum is at the
+// same earliest time as the largest S/N.  Otherwise the value is the S/N.
+template <int NW, bool kGuard, bool kSums>
+__device__ __forceinline__ void boxcars(const double* P, int ni, int L, int t0, const double* base,
+                                        const double* inv, double* bs, int* bt) {
+  for (int i = threadIdx.x; i < ni; i += kDetThreads) {
+    double q[NW + 1];
+    q[0] = P[i];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) q[k + 1] = P[kGuard ? min(i + (1 << k), L) : i + (1 << k)];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      double v;
+      if constexpr (kSums)
+        v = q[k + 1] - q[0];
+      else
+        v = (q[k + 1] - q[0] - base[k]) * inv[k];
+      // times increase along a thread, so the first of equals stays
+      const bool take = v > bs[k] && (!kGuard || i + (1 << k) <= L);
+      bs[k] = take ? v : bs[k];
+      bt[k] = take ? t0 + i : bt[k];
+    }
+  }
+}
+
+template <typename T, int NW>
+__global__ __launch_bounds__(kDetThreads) void detect_rows(const T* __restrict__ out, int64_t nsamp,
                                                            double threshold, double* __restrict__ stats,
                                                            double* __restrict__ best_snr,
                                                            int32_t* __restrict__ best_t,
                                                            dedisp_candidate* __restrict__ cand, int cap,
                                                            unsigned* __restrict__ count) {
-  extern __shared__ double sh[];  // [kDetChunk + 2^(nw-1)] prefix sums, reused for the reductions
+  extern __shared__ double sh[];  // [kDetChunk + 2^(NW-1)] prefix sums, reused for the reductions
   __shared__ double red[kDetThreads];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -58,10 +99,25 @@ __global__ __launch_bounds__(kDetThreads) void detect_rows(const T* __restrict__
   const int d = blockIdx.x;
   const T* row = out + static_cast<int64_t>(d) * nsamp;
 
-  // moments about the first value (no cancellation for rows far from zero)
+  constexpr bool kSums = std::is_same<T, int32_t>::value;  // track sums, S/N at the end
+
+  // moments about the first value (no cancellation for rows far from zero):
+  // a pass of their own for float rows, whose S/N every start needs; integer
+  // rows add them up while the chunks are loaded
   const double k0 = static_cast<double>(row[0]);
   double s1 = 0.0, s2 = 0.0;
-  for (int64_t t = tid; t < nsamp; t += kUnroll * kDetThreads) {
+  double mean = 0.0, sd = 0.0;
+  auto finish_moments = [&]() {
+    const double m1 = block_sum(s1, red) / static_cast<double>(nsamp);
+    const double m2 = block_sum(s2, red) / static_cast<double>(nsamp);
+    mean = k0 + m1;
+    sd = sqrt(fmax(m2 - m1 * m1, 0.0));
+    if (stats != nullptr && tid == 0) {
+      stats[2 * d] = mean;
+      stats[2 * d + 1] = sd;
+    }
+  };
+  for (int64_t t = tid; !kSums && t < nsamp; t += kUnroll * kDetThreads) {
     double v[kUnroll];  // independent loads, all in flight before the first is used
 #pragma unroll
     for (int j = 0; j < kUnroll; ++j) {
@@ -76,25 +132,23 @@ __global__ __launch_bounds__(kDetThreads) void detect_rows(const T* __restrict__
       s2 += e * e;
     }
   }
-  const double m1 = block_sum(s1, red) / static_cast<double>(nsamp);
-  const double m2 = block_sum(s2, red) / static_cast<double>(nsamp);
-  const double mean = k0 + m1;
-  const double sd = sqrt(fmax(m2 - m1 * m1, 0.0));
-  if (stats != nullptr && tid == 0) {
-    stats[2 * d] = mean;
-    stats[2 * d + 1] = sd;
-  }
+  if constexpr (!kSums) finish_moments();
 
-  const int W = 1 << (nw - 1);
-  const int span = kDetChunk + W - 1;
-  double inv[kMaxDetectWidths], base[kMaxDetectWidths];
-  double bs[kMaxDetectWidths];
-  int64_t bt[kMaxDetectWidths];
+  constexpr int W = 1 << (NW - 1);
+  constexpr int span = kDetChunk + W - 1;
+  constexpr int NS = kSums ? 1 : NW;  // integer rows need the S/N terms only at the end
+  double base[NS] = {}, inv[NS] = {};
+  if constexpr (!kSums) {
 #pragma unroll
-  for (int k = 0; k < kMaxDetectWidths; ++k) {
-    const double w = static_cast<double>(1 << k);
-    inv[k] = sd > 0.0 ? 1.0 / (sd * sqrt(w)) : 0.0;
-    base[k] = w * mean;
+    for (int k = 0; k < NS; ++k) {
+      base[k] = snr_base(k, mean);
+      inv[k] = snr_scale(k, sd);
+    }
+  }
+  double bs[NW];  // best value (S/N, or the boxcar sum for integer rows) of this thread's starts
+  int bt[NW];     // its time; times are below 2^31 (nsamp is checked)
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
     bs[k] = -INFINITY;
     bt[k] = -1;
   }
@@ -111,10 +165,20 @@ __global__ __launch_bounds__(kDetThreads) void detect_rows(const T* __restrict__
 #pragma unroll
       for (int j = 0; j < kUnroll; ++j)
         if (i + j * kDetThreads < L) P[i + j * kDetThreads] = v[j];
+      if constexpr (kSums) {
+        // each sample once: the chunk's own samples, not the overlap into the next
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+          const double e = i + j * kDetThreads < min(L, kDetChunk) ? v[j] - k0 : 0.0;
+          s1 += e;
+          s2 += e * e;
+        }
+      }
     }
     __syncthreads();
-    // in place: P[i] = sum of the chunk's samples before i, P[L] = all of them
-    const int seg = (L + kDetThreads - 1) / kDetThreads;
+    // in place: P[i] = sum of the chunk's samples before i, P[L] = all of them.
+    // Runs of an odd length start on different LDS banks.
+    const int seg = ((L + kDetThreads - 1) / kDetThreads) | 1;
     const int i0 = min(tid * seg, L), i1 = min(i0 + seg, L);
     double own = 0.0;
     for (int i = i0; i < i1; ++i) own += P[i];
@@ -136,60 +200,49 @@ __global__ __launch_bounds__(kDetThreads) void detect_rows(const T* __restrict__
     if (i1 == L && i0 < i1) P[L] = run;
     if (L == 0 && tid == 0) P[0] = 0.0;
     __syncthreads();
-    // complete boxcars starting in this chunk: i < kDetChunk and t0 + i + w <= nsamp
+    // complete boxcars starting in this chunk: i < kDetChunk and t0 + i + w <= nsamp;
+    // a chunk that holds its whole span has them all
     const int ni = min(kDetChunk, L);
-    for (int i = tid; i < ni; i += kDetThreads) {
-      const double p0 = P[i];
-      // fully unrolled (uniform guards only), so that bs/bt stay in registers
-#pragma unroll
-      for (int k = 0; k < kMaxDetectWidths; ++k) {
-        if (k < nw) {
-          const int w = 1 << k;
-          const bool fits = i + w <= L;  // a complete boxcar
-          const double snr = (P[fits ? i + w : L] - p0 - base[k]) * inv[k];
-          if (fits && snr > bs[k]) {  // times increase along a thread, so the first of equals stays
-            bs[k] = snr;
-            bt[k] = t0 + i;
-          }
-        }
-      }
-    }
+    if (L == span)
+      boxcars<NW, false, kSums>(P, ni, L, static_cast<int>(t0), base, inv, bs, bt);
+    else
+      boxcars<NW, true, kSums>(P, ni, L, static_cast<int>(t0), base, inv, bs, bt);
     __syncthreads();  // the chunk's sums are read before the next load
   }
+  if constexpr (kSums) finish_moments();
 
   // best over the workgroup, per width: largest S/N, then earliest time
   double* rs = sh;
-  int64_t* rt = reinterpret_cast<int64_t*>(sh + kDetThreads * nw);
+  int* rt = reinterpret_cast<int*>(sh + kDetThreads * NW);
 #pragma unroll
-  for (int k = 0; k < kMaxDetectWidths; ++k) {
-    if (k < nw) {
-      rs[k * kDetThreads + tid] = bs[k];
-      rt[k * kDetThreads + tid] = bt[k];
-    }
+  for (int k = 0; k < NW; ++k) {
+    // the S/N of the best sum, the same expression as for every start
+    rs[k * kDetThreads + tid] = kSums && bt[k] >= 0 ? (bs[k] - snr_base(k, mean)) * snr_scale(k, sd) : bs[k];
+    rt[k * kDetThreads + tid] = bt[k];
   }
   __syncthreads();
-  if (tid < nw) {
+  if (tid < NW) {
     const int k = tid;
     double v = -INFINITY;
-    int64_t tb = -1;
+    int tb = -1;
     for (int j = 0; j < kDetThreads; ++j) {
       const double x = rs[k * kDetThreads + j];
-      const int64_t tx = rt[k * kDetThreads + j];
+      const int tx = rt[k * kDetThreads + j];
       if (tx < 0) continue;
       if (tb < 0 || x > v || (x == v && tx < tb)) {
         v = x;
         tb = tx;
       }
     }
-    best_snr[static_cast<int64_t>(d) * nw + k] = v;
-    best_t[static_cast<int64_t>(d) * nw + k] = static_cast<int32_t>(tb);
+    best_snr[static_cast<int64_t>(d) * NW + k] = v;
+    best_t[static_cast<int64_t>(d) * NW + k] = tb;
     if (tb >= 0 && v >= threshold && cand != nullptr) {
       const unsigned idx = atomicAdd(count, 1u);
       if (static_cast<int>(idx) < cap) {
         dedisp_candidate c;
         c.dm_index = d;
         c.width = 1 << k;
-        c.time = static_cast<int32_t>(tb);
+        c.time = tb;
         c.snr = static_cast<float>(v);
         cand[idx] = c;
       }
@@ -226,25 +279,56 @@ size_t detect_lds_bytes(int nwidths) {
   return boxes > reduce ? boxes : reduce;
 }
 
+namespace {
+
+template <typename T, int NW>
+int launch_detect(int nrows, const T* out, int64_t nsamp, double threshold, double* stats, double* best_snr,
+                  int32_t* best_t, dedisp_candidate* cand, int cap, unsigned* count, hipStream_t s) {
+  const void* fn = reinterpret_cast<const void*>(&detect_rows<T, NW>);
+  const int st = allow_detect_lds(fn);
+  if (st != DEDISP_OK) return st;
+  hipLaunchKernelGGL((detect_rows<T, NW>), dim3(static_cast<unsigned>(nrows)), dim3(kDetThreads),
+                     detect_lds_bytes(NW), s, out, nsamp, threshold, stats, best_snr, best_t, cand, cap, count);
+  return DEDISP_HIP_STATUS(hipGetLastError());
+}
+
+template <typename T>
+int launch_detect_any(int nw, int nrows, const T* out, int64_t nsamp, double threshold, double* stats,
+                      double* best_snr, int32_t* best_t, dedisp_candidate* cand, int cap, unsigned* count,
+                      hipStream_t s) {
+  static_assert(kMaxDetectWidths == 12, "one instantiation per number of widths");
+#define DEDISP_DETECT_CASE(N) \
+  case N:                     \
+    return launch_detect<T, N>(nrows, out, nsamp, threshold, stats, best_snr, best_t, cand, cap, count, s);
+  switch (nw) {
+    DEDISP_DETECT_CASE(1)
+    DEDISP_DETECT_CASE(2)
+    DEDISP_DETECT_CASE(3)
+    DEDISP_DETECT_CASE(4)
+    DEDISP_DETECT_CASE(5)
+    DEDISP_DETECT_CASE(6)
+    DEDISP_DETECT_CASE(7)
+    DEDISP_DETECT_CASE(8)
+    DEDISP_DETECT_CASE(9)
+    DEDISP_DETECT_CASE(10)
+    DEDISP_DETECT_CASE(11)
+    DEDISP_DETECT_CASE(12)
+    default:
+      return DEDISP_ERR_INVALID_ARG;
+  }
+#undef DEDISP_DETECT_CASE
+}
+
+}  // namespace
+
 int detect(dedisp_plan p, const void* out, int64_t nsamp, int nwidths, double threshold, double* stats,
            double* best_snr, int32_t* best_t, dedisp_candidate* cand, int cap, unsigned* count, hipStream_t s) {
-  const size_t lds = detect_lds_bytes(nwidths);
   if (cand != nullptr) hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, s, count);
-  if (p->dtype == DEDISP_U8) {
-    const void* fn = reinterpret_cast<const void*>(&detect_rows<int32_t>);
-    int st = allow_detect_lds(fn);
-    if (st != DEDISP_OK) return st;
-    hipLaunchKernelGGL(detect_rows<int32_t>, dim3(p->ndm), dim3(kDetThreads), lds, s,
-                       static_cast<const int32_t*>(out), nsamp, nwidths, threshold, stats, best_snr, best_t, cand,
-                       cap, count);
-  } else {
-    const void* fn = reinterpret_cast<const void*>(&detect_rows<float>);
-    int st = allow_detect_lds(fn);
-    if (st != DEDISP_OK) return st;
-    hipLaunchKernelGGL(detect_rows<float>, dim3(p->ndm), dim3(kDetThreads), lds, s, static_cast<const float*>(out),
-                       nsamp, nwidths, threshold, stats, best_snr, best_t, cand, cap, count);
-  }
-  return DEDISP_HIP_STATUS(hipGetLastError());
+  if (p->dtype == DEDISP_U8)
+    return launch_detect_any(nwidths, p->ndm, static_cast<const int32_t*>(out), nsamp, threshold, stats, best_snr,
+                             best_t, cand, cap, count, s);
+  return launch_detect_any(nwidths, p->ndm, static_cast<const float*>(out), nsamp, threshold, stats, best_snr,
+                           best_t, cand, cap, count, s);
 }
 
 }  // namespace dedisp

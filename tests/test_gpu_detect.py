@@ -110,6 +110,19 @@ def test_detect_edge_shapes(dd, n, nw):
     compare(got, oracle.detect(block, nw, 1.0), block, 1.0, exact_t=True)
 
 
+@pytest.mark.parametrize("nw", [10, 12])
+def test_detect_int_ties(dd, nw):
+    """Integer rows of a few levels (negative ones too): every width has many
+    starts with equal sums, so the earliest one must be reported; chunks end
+    inside the widest boxcars and the last chunk is partial."""
+    rng = np.random.default_rng([24, nw])
+    block = rng.integers(-3, 4, size=(9, 20000)).astype(np.int32)
+    block[4] = -7  # constant
+    plan = plan_for(dd, 9, "u8")
+    got = run_detect(dd, plan, block, nw, 2.0)
+    compare(got, oracle.detect(block, nw, 2.0), block, 2.0, exact_t=True)
+
+
 def test_detect_capacity_and_count(dd):
     """More candidates than room: the count is the true number, only the
     capacity is written."""
