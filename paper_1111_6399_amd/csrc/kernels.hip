@@ -411,11 +411,12 @@ __device__ __forceinline__ void lds_barrier_asm() {
 //
 // Channels are processed in stages of CG, two stages alternating in LDS (one
 // slot per channel).  Channel c0 + g of every stage is loaded by the first
-// wave of group g (of NW/CG waves): right after the barrier that frees its
-// slot it issues the slot's 1 KB loads, and before the next barrier it waits
-// for them (it has nothing else in flight), so the barrier makes the stage
-// visible.  The scalar cost of staging is paid by one wave per channel.  A slot has room for the widest window of
-// the plan; each window takes the 1 KB loads that cover what its tile reads.
+// IW waves of group g (of NW/CG waves), 4 KB in turn: right after the barrier
+// that frees its slot each issues its share of the slot's 1 KB loads, and
+// before the next barrier it waits for them (it has nothing else in flight),
+// so the barrier makes the stage visible.  A slot has room for the widest
+// window of the plan; each window takes the 1 KB loads that cover what its
+// tile reads.
 // The loads of a channel go through a buffer descriptor based at its row
 // (rounded down to 16 bytes) that reaches to the end of the input, so offsets
 // stay 32-bit however large the input is, and loads past its end return
@@ -436,7 +437,7 @@ __device__ __forceinline__ void lds_barrier_asm() {
 // 32-bit totals every 256 channels.  Float sums: channels ascending, summed in
 // blocks of kChanBlock into a partial that is then added to the total (the
 // same order in every variant).
-template <bool kPairs, int DW, int KS, int WD, int WT, int CG>
+template <bool kPairs, int DW, int KS, int WD, int WT, int CG, int IW>
 __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_tile) {
   constexpr int NW = WD * WT;
   constexpr int SPW = 126 * KS;
@@ -450,6 +451,7 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
   constexpr int FLUSH = kPairs ? 256 : kChanBlock;
   static_assert(KS % 2 == 0 && (D - 1) * NR <= 15, "tile shape");
   static_assert(NW % CG == 0 && FLUSH % CG == 0, "stage shape");
+  static_assert(IW >= 1 && IW <= WPG, "waves that load a window");
   static_assert((SPW * ES) % 8 == 0, "time offset of a wave keeps the read alignment");
   extern __shared__ float4 lds4[];
 
@@ -495,17 +497,17 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
     return ES * ((static_cast<int64_t>(c) * a.pitch) & ~static_cast<int64_t>(ALIGN - 1));
   };
   // Loads of channel c (this group's channel of a stage: window offset wbase
-  // from its row base, `runs` loads) into the slot at LDS byte offset slot,
-  // issued by the group's first wave; a channel past the last one gets zeros
-  // instead.
+  // from its row base, `runs` loads) into the slot at LDS byte offset slot:
+  // the group's first IW waves issue them, 4 KB each in turn; a channel past
+  // the last one gets zeros (from the first wave) instead.
   auto issue = [&](int c, uint32_t wbase, int runs, uint32_t slot) {
-    if (gq != 0) return;
     if (c < nchans) {
+      if (gq >= IW || 4 * gq >= runs) return;
       const int64_t rb = row_base(c);
       const v4i rs = buffer_words(static_cast<const char*>(a.in) + rb, a.total4 * ES - rb);
-      uint32_t lds = __builtin_amdgcn_readfirstlane(lds0 + slot);
-      uint32_t voff = wbase + t0b + lane16;
-      for (int i = 0; i < runs; i += 4, lds += 4096u, voff += 4096u) {
+      uint32_t lds = __builtin_amdgcn_readfirstlane(lds0 + slot + 4096u * gq);
+      uint32_t voff = wbase + t0b + lane16 + 4096u * gq;
+      for (int i = 4 * gq; i < runs; i += 4 * IW, lds += 4096u * IW, voff += 4096u * IW) {
         const int k = runs - i;
         if (k >= 4)
           lds_dma_runs<4>(lds, voff, rs);
@@ -516,7 +518,7 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
         else
           lds_dma_runs<1>(lds, voff, rs);
       }
-    } else if (c < nstages * CG) {
+    } else if (c < nstages * CG && gq == 0) {
       for (int m = 0; m < a.runs; ++m)
         *reinterpret_cast<float4*>(reinterpret_cast<char*>(lds4) + slot + 1024u * m + lane16) =
             make_float4(0.f, 0.f, 0.f, 0.f);
@@ -526,9 +528,10 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
   // input, if the slot holds it, is patched in by the lane that loaded its
   // place.
   auto patch = [&](int c, uint32_t wbase, int runs, uint32_t slot) {
-    if (kPairs || gq != 0 || c >= nchans || c < c_tail) return;
+    if (kPairs || c >= nchans || c < c_tail) return;
     const int64_t off = static_cast<int64_t>(a.total4) * 4 - (row_base(c) + wbase + t0b);
     if (off < 0 || off >= 1024 * static_cast<int64_t>(runs)) return;
+    if ((off >> 12) % IW != gq) return;  // the wave that loaded its 4 KB
     const uint32_t o = static_cast<uint32_t>(off);
     if (lane == ((o >> 4) & 63))
       *reinterpret_cast<float4*>(reinterpret_cast<char*>(lds4) + slot + o) =
@@ -759,11 +762,11 @@ __global__ __launch_bounds__(256) void assemble_window(const St* __restrict__ pr
 
 // One launch of a tile variant: 8-bit input (widened to 16 bits) as pairs,
 // float and half input (widened to float) as float32.
-template <bool kPairs, int DW, int KS, int WD, int WT, int CG>
+template <bool kPairs, int DW, int KS, int WD, int WT, int CG, int IW>
 __global__ __launch_bounds__(64 * WD * WT) void dedisp_tiled(const TiledArgs a) {
   int dm_tile, t_tile;
   if (!tile_of(a, dm_tile, t_tile)) return;  // padding block of the last group
-  tile_dma<kPairs, DW, KS, WD, WT, CG>(a, dm_tile, t_tile);
+  tile_dma<kPairs, DW, KS, WD, WT, CG, IW>(a, dm_tile, t_tile);
 }
 
 // Widening of the inputs of a batch: blockIdx.y selects the job, the blocks
@@ -799,7 +802,7 @@ __global__ __launch_bounds__(256) void widen_job_kernel(const WidenJob* __restri
 // tile) items from one atomic counter until none are left.  Items are
 // numbered beam by beam, beams in order of decreasing cost per item (longest
 // items first), and inside a beam in the same groups as a single launch.
-template <int DW, int KS, int WD, int WT, int CG>
+template <int DW, int KS, int WD, int WT, int CG, int IW>
 __global__ __launch_bounds__(64 * WD * WT) void dedisp_batch_persistent(const BatchArgs b) {
   __shared__ long long item_s;
   for (;;) {
@@ -826,9 +829,9 @@ __global__ __launch_bounds__(64 * WD * WT) void dedisp_batch_persistent(const Ba
     if (dm_tile < a.n_dm_tiles && t_tile < a.n_t_tiles) {
       // 8-bit input is staged as 16-bit pairs, half and float as float
       if (((cint32*)(b.dtype))[beam] == DEDISP_U8)
-        tile_dma<true, DW, KS, WD, WT, CG>(a, dm_tile, t_tile);
+        tile_dma<true, DW, KS, WD, WT, CG, IW>(a, dm_tile, t_tile);
       else
-        tile_dma<false, DW, KS, WD, WT, CG>(a, dm_tile, t_tile);
+        tile_dma<false, DW, KS, WD, WT, CG, IW>(a, dm_tile, t_tile);
     }
     lds_barrier();  // every wave is done with this item's LDS before the next
   }
@@ -845,26 +848,30 @@ struct Variant {
   const void* batch;  // persistent batch kernel
 };
 
-#define DEDISP_VARIANT(DW, KS, WD, WT, CG)                                                          \
+#define DEDISP_VARIANT(DW, KS, WD, WT, CG, IW)                                                      \
   Variant {                                                                                        \
     TileShape{DW, KS, WD, WT}, CG,                                                                 \
-        {reinterpret_cast<const void*>(&dedisp_tiled<true, DW, KS, WD, WT, CG>),                    \
-         reinterpret_cast<const void*>(&dedisp_tiled<false, DW, KS, WD, WT, CG>),                   \
-         reinterpret_cast<const void*>(&dedisp_tiled<false, DW, KS, WD, WT, CG>)},                  \
-        reinterpret_cast<const void*>(&dedisp_batch_persistent<DW, KS, WD, WT, CG>)                 \
+        {reinterpret_cast<const void*>(&dedisp_tiled<true, DW, KS, WD, WT, CG, IW>),                \
+         reinterpret_cast<const void*>(&dedisp_tiled<false, DW, KS, WD, WT, CG, IW>),               \
+         reinterpret_cast<const void*>(&dedisp_tiled<false, DW, KS, WD, WT, CG, IW>)},              \
+        reinterpret_cast<const void*>(&dedisp_batch_persistent<DW, KS, WD, WT, CG, IW>)             \
   }
 
+// The last argument is the number of waves of a group that share a window's
+// loads (4 KB each in turn): a single loading wave is late to every stage's
+// barrier by the time it spends issuing, so groups of 4 or 8 waves share the
+// work; with 2 waves a group (4 channels per stage) sharing measured slower.
 const Variant kVariants[] = {
-    DEDISP_VARIANT(2, 8, 4, 2, 2),  // 8 trials x 2016 samples, 512 threads (several workgroups per CU)
-    DEDISP_VARIANT(2, 8, 8, 2, 2),  // 16 x 2016, 1024 threads
-    DEDISP_VARIANT(4, 8, 4, 2, 2),  // 16 x 2016, 512 threads
-    DEDISP_VARIANT(2, 8, 4, 4, 2),  // 8 x 4032, 1024 threads
-    DEDISP_VARIANT(2, 8, 4, 2, 4),  // 8 x 2016, 512 threads, 4 channels per stage
-    DEDISP_VARIANT(2, 8, 8, 2, 4),  // 16 x 2016, 1024 threads, 4 channels per stage
-    DEDISP_VARIANT(4, 8, 4, 2, 4),  // 16 x 2016, 512 threads, 4 channels per stage
-    DEDISP_VARIANT(2, 8, 4, 2, 1),  // 8 x 2016, 512 threads, 1 channel per stage
-    DEDISP_VARIANT(4, 8, 8, 1, 2),  // 32 x 1008, 512 threads
-    DEDISP_VARIANT(2, 4, 8, 2, 2),  // 16 x 1008, 1024 threads
+    DEDISP_VARIANT(2, 8, 4, 2, 2, 4),  // 8 trials x 2016 samples, 512 threads (several workgroups per CU)
+    DEDISP_VARIANT(2, 8, 8, 2, 2, 2),  // 16 x 2016, 1024 threads
+    DEDISP_VARIANT(4, 8, 4, 2, 2, 4),  // 16 x 2016, 512 threads
+    DEDISP_VARIANT(2, 8, 4, 4, 2, 2),  // 8 x 4032, 1024 threads
+    DEDISP_VARIANT(2, 8, 4, 2, 4, 1),  // 8 x 2016, 512 threads, 4 channels per stage
+    DEDISP_VARIANT(2, 8, 8, 2, 4, 4),  // 16 x 2016, 1024 threads, 4 channels per stage
+    DEDISP_VARIANT(4, 8, 4, 2, 4, 1),  // 16 x 2016, 512 threads, 4 channels per stage
+    DEDISP_VARIANT(2, 8, 4, 2, 1, 2),  // 8 x 2016, 512 threads, 1 channel per stage
+    DEDISP_VARIANT(4, 8, 8, 1, 2, 4),  // 32 x 1008, 512 threads
+    DEDISP_VARIANT(2, 4, 8, 2, 2, 2),  // 16 x 1008, 1024 threads
 };
 constexpr int kNumTiled = sizeof(kVariants) / sizeof(kVariants[0]);
 
