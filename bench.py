@@ -175,6 +175,14 @@ def run_batch(args) -> dict:
     op = [o.data_ptr() for o in outs]
     stream = torch.cuda.current_stream()
 
+    # each plan tuned on its own first: the plain form runs with these, and the
+    # batch's autotune also tries the split that follows them
+    t = time.perf_counter()
+    for p, w in zip(plans, beams):
+        if args.variant < 0:
+            dd.dedisp_autotune(p.handle, w.nsamp)
+    log("per-beam autotune %.1f s" % (time.perf_counter() - t))
+
     batch = dd.dedisp_batch_create([p.handle for p in plans], [w.nsamp for w in beams])
     try:
         t = time.perf_counter()
@@ -216,11 +224,6 @@ def run_batch(args) -> dict:
         ok = ok and good
 
     # the plain form: one launch per beam on one stream, each plan tuned on its own
-    t = time.perf_counter()
-    for p, w in zip(plans, beams):
-        if args.variant < 0:
-            dd.dedisp_autotune(p.handle, w.nsamp)
-    log("per-beam autotune %.1f s" % (time.perf_counter() - t))
 
     def plain():
         for p, w, x, o in zip(plans, beams, ins, outs):

@@ -275,7 +275,9 @@ int dedisp_execute_cpu(dedisp_plan plan, const void *in_host, void *out_host, in
 
 /*
  * A batch runs many independent beams (plans of any shape and dtype, each with
- * its own output length) in ONE persistent launch, replayed from a HIP graph.
+ * its own output length) in persistent launches (one per group of beams with
+ * the same tile variant, staging kind and LDS occupancy), replayed from a HIP
+ * graph.
  * Work is cut into (beam, DM tile, time tile) items, ordered longest first, and
  * pulled by resident workgroups from an atomic counter.  Each beam's result is
  * identical to dedisp_execute of that beam alone.
@@ -295,14 +297,23 @@ int dedisp_batch_execute(dedisp_batch batch, const void *const *ins, void *const
  * both are 0 before the first execute). */
 int dedisp_batch_info(dedisp_batch batch, int64_t *work_items, int *workgroups);
 
-/* Tile variant of the persistent kernel (>= 1).  Setting it rebuilds the
- * graph on the next execute; it synchronises the batch's device. */
+/* Tile variant of the persistent kernel (>= 1; -1 if no beam runs in it).
+ * Setting v >= 1 runs every beam that variant fits in the persistent kernel
+ * (the rest on their own); setting 0 splits by each plan's own variant (the
+ * persistent kernel takes the variant that carries the most work, the other
+ * beams run on their own, each with its plan's variant).  Setting rebuilds
+ * the graph on the next execute; it synchronises the batch's device. */
 int dedisp_batch_get_variant(dedisp_batch batch, int *variant);
 int dedisp_batch_set_variant(dedisp_batch batch, int variant);
 
-/* Time the batch with every tile variant that fits any of its beams, on the
- * given buffers, and keep the fastest.  Synchronises the stream.  The outputs
- * are overwritten (with correct results).  best_ms may be NULL. */
+/* Time the batch with every tile variant that fits any of its beams; with
+ * 8-bit and float beams mixed, also each variant for the 8-bit beams with the
+ * float beams' held, then each for the float beams (the two kinds run as
+ * separate persistent kernels); and the split that follows each plan's own
+ * variant (set or tuned with dedisp_autotune).  Keeps the fastest;
+ * best_variant is then the variant of the persistent kernel that carries the
+ * most work.  Synchronises the stream.  The outputs are overwritten (with
+ * correct results).  best_ms may be NULL. */
 int dedisp_batch_autotune(dedisp_batch batch, const void *const *ins, void *const *outs, void *stream,
                           int *best_variant, double *best_ms);
 

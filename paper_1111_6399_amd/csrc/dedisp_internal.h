@@ -83,13 +83,17 @@ struct WidenJob {
   int dtype;
 };
 
+// A persistent batch kernel's work counters: one per XCD (chip), items handed
+// out in chunks of kBatchChunk consecutive ones.
+constexpr int kBatchCounters = 8;
+constexpr int kBatchChunk = 32;
+
 struct BatchArgs {
-  const TiledArgs* beams;   // [nbeams]
+  const TiledArgs* beams;   // [nbeams], all staged alike (16-bit pairs or float)
   const int64_t* item_end;  // [nbeams] inclusive prefix sums of work items
-  const int* dtype;         // [nbeams]
   int nbeams;
   int64_t n_items;
-  unsigned long long* counter;
+  unsigned long long* counter;  // [kBatchCounters]
 };
 
 }  // namespace dedisp
@@ -137,6 +141,9 @@ TileShape variant_shape(int v);   // v >= 1
 // Largest window (in samples) a tiled variant can stage for this plan, and
 // whether the plan fits it.
 bool variant_fits(dedisp_plan p, int v);
+// Workgroups of tiled variant v that LDS lets share a CU for this plan (0 if
+// it does not fit).
+int tiled_per_cu(dedisp_plan p, int v);
 int default_variant(dedisp_plan p);
 
 // Launch one plan's kernel over the whole problem.  8-bit and half input is
@@ -178,9 +185,11 @@ int corner_turn(const void* in, void* out, int64_t nsamp, int nchans, int64_t pi
 size_t detect_lds_bytes(int nwidths);
 int detect(dedisp_plan p, const void* out, int64_t nsamp, int nwidths, double threshold, double* stats,
            double* best_snr, int32_t* best_t, dedisp_candidate* cand, int cap, unsigned* count, hipStream_t s);
-// Persistent batch kernel of variant v >= 1, and the counter reset kernel.
-const void* batch_kernel(int v);
+// Persistent batch kernel of variant v >= 1 for beams staged as 16-bit pairs
+// (8-bit input) or as float, and the counter reset kernel.
+const void* batch_kernel(int v, bool pairs);
 const void* reset_kernel();
+int reset_kernel_threads();  // block size of the reset kernel (zeroes kBatchCounters counters)
 
 
 // True when the environment variable DEDISP_TRACE is set: failing HIP calls

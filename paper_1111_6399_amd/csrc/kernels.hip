@@ -605,15 +605,12 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
     // the other stage's slots are free: issue this group's channel of the next stage
     issue(c0 + CG + grp, static_cast<uint32_t>(wnext), rnext, (sbase ^ (CG * slot_bytes)) + grp * slot_bytes);
 
-    uint32_t ba[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int u = b / DW, j = b % DW;
-      ba[b] = block_addr(vlane + sbase + u * slot_bytes, q[u][j]);
-    }
+    // read address of block b (channel c0 + b / DW, trial b % DW), formed right
+    // before its reads so that only the blocks in flight hold one
+    auto ba = [&](int b) { return block_addr(vlane + sbase + (b / DW) * slot_bytes, q[b / DW][b % DW]); };
     v2u rb[D][NR];
 #pragma unroll
-    for (int b = 0; b < D && b < NB; ++b) lds_reads<NR>(ba[b], rb[b]);
+    for (int b = 0; b < D && b < NB; ++b) lds_reads<NR>(ba(b), rb[b]);
     // scalar loads for later stages, consumed a stage from now
 #pragma unroll
     for (int u = 0; u < CG; ++u)
@@ -635,7 +632,7 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
         TrialAdds<NR>::u8(acc0[b % DW], acc1[b % DW], rb[b % D], q[b / DW][b % DW]);
       else
         TrialAdds<NR>::f32(acc0[b % DW], rb[b % D], q[b / DW][b % DW]);
-      if (b + D < NB) lds_reads<NR>(ba[b + D], rb[(b + D) % D]);
+      if (b + D < NB) lds_reads<NR>(ba(b + D), rb[(b + D) % D]);
     }
     if (((c0 + CG) % FLUSH) == 0) flush();
 #pragma unroll
@@ -801,17 +798,27 @@ __global__ __launch_bounds__(256) void widen_job_kernel(const WidenJob* __restri
 // Persistent batch kernel: resident workgroups pull (beam, trial tile, time
 // tile) items from one atomic counter until none are left.  Items are
 // numbered beam by beam, beams in order of decreasing cost per item (longest
-// items first), and inside a beam in the same groups as a single launch.
-template <int DW, int KS, int WD, int WT, int CG, int IW>
+// items first), and inside a beam in the same groups as a single launch.  One
+// kernel per staging kind (its beams are all 8-bit, or all float and half),
+// so that each carries the registers of one path only.
+template <bool kPairs, int DW, int KS, int WD, int WT, int CG, int IW>
 __global__ __launch_bounds__(64 * WD * WT) void dedisp_batch_persistent(const BatchArgs b) {
   __shared__ long long item_s;
+  // Blocks run on XCD blockIdx.x mod 8.  Items go out in chunks of
+  // kBatchChunk consecutive ones (neighbouring tiles of a beam, whose windows
+  // overlap), chunk j to counter j mod nx: the workgroups of one XCD share a
+  // counter, so a chunk stays in one L2, and every XCD gets the same mix of
+  // beams.  (With fewer than 8 workgroups, nx = the grid.)
+  const int nx = gridDim.x < 8 ? static_cast<int>(gridDim.x) : 8;
+  const int xcd = static_cast<int>(blockIdx.x) % nx;
   for (;;) {
-    if (threadIdx.x == 0) item_s = static_cast<long long>(atomicAdd(b.counter, 1ull));
+    if (threadIdx.x == 0) item_s = static_cast<long long>(atomicAdd(b.counter + xcd, 1ull));
     lds_barrier();
-    const long long item =
+    const long long k =
         static_cast<long long>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(item_s)))) |
         (static_cast<long long>(__builtin_amdgcn_readfirstlane(static_cast<int>(item_s >> 32))) << 32);
-    if (item >= b.n_items) return;
+    const long long item = (k / kBatchChunk) * (nx * kBatchChunk) + xcd * kBatchChunk + k % kBatchChunk;
+    if (item >= b.n_items) return;  // the counter's later items are further on
     typedef __attribute__((address_space(4))) const int64_t cint64;
     typedef __attribute__((address_space(4))) const TiledArgs ctargs;
     cint64* ends = (cint64*)(b.item_end);
@@ -824,20 +831,17 @@ __global__ __launch_bounds__(64 * WD * WT) void dedisp_batch_persistent(const Ba
     const int bs = a.gd * a.gt;
     const int g = l / bs;
     const int i = l - g * bs;
-    const int dm_tile = (g % a.n_dm_groups) * a.gd + i % a.gd;
-    const int t_tile = (g / a.n_dm_groups) * a.gt + i / a.gd;
-    if (dm_tile < a.n_dm_tiles && t_tile < a.n_t_tiles) {
-      // 8-bit input is staged as 16-bit pairs, half and float as float
-      if (((cint32*)(b.dtype))[beam] == DEDISP_U8)
-        tile_dma<true, DW, KS, WD, WT, CG, IW>(a, dm_tile, t_tile);
-      else
-        tile_dma<false, DW, KS, WD, WT, CG, IW>(a, dm_tile, t_tile);
-    }
+    // wave-uniform: kept in scalar registers (the divisions above run on the vector unit)
+    const int dm_tile = __builtin_amdgcn_readfirstlane((g % a.n_dm_groups) * a.gd + i % a.gd);
+    const int t_tile = __builtin_amdgcn_readfirstlane((g / a.n_dm_groups) * a.gt + i / a.gd);
+    if (dm_tile < a.n_dm_tiles && t_tile < a.n_t_tiles) tile_dma<kPairs, DW, KS, WD, WT, CG, IW>(a, dm_tile, t_tile);
     lds_barrier();  // every wave is done with this item's LDS before the next
   }
 }
 
-__global__ void reset_counter(unsigned long long* c) { *c = 0ull; }
+__global__ void reset_counter(unsigned long long* c) {
+  if (threadIdx.x < kBatchCounters) c[threadIdx.x] = 0ull;
+}
 
 // ----------------------------------------------------------- registry --
 
@@ -845,7 +849,7 @@ struct Variant {
   TileShape shape;
   int cg;             // channels per stage
   const void* fn[3];  // by dtype: U8, F16, F32
-  const void* batch;  // persistent batch kernel
+  const void* batch[2];  // persistent batch kernel: float staging, 16-bit pair staging
 };
 
 #define DEDISP_VARIANT(DW, KS, WD, WT, CG, IW)                                                      \
@@ -854,7 +858,8 @@ struct Variant {
         {reinterpret_cast<const void*>(&dedisp_tiled<true, DW, KS, WD, WT, CG, IW>),                \
          reinterpret_cast<const void*>(&dedisp_tiled<false, DW, KS, WD, WT, CG, IW>),               \
          reinterpret_cast<const void*>(&dedisp_tiled<false, DW, KS, WD, WT, CG, IW>)},              \
-        reinterpret_cast<const void*>(&dedisp_batch_persistent<DW, KS, WD, WT, CG, IW>)             \
+        {reinterpret_cast<const void*>(&dedisp_batch_persistent<false, DW, KS, WD, WT, CG, IW>),      \
+         reinterpret_cast<const void*>(&dedisp_batch_persistent<true, DW, KS, WD, WT, CG, IW>)}       \
   }
 
 // The last argument is the number of waves of a group that share a window's
@@ -872,6 +877,7 @@ const Variant kVariants[] = {
     DEDISP_VARIANT(2, 8, 4, 2, 1, 2),  // 8 x 2016, 512 threads, 1 channel per stage
     DEDISP_VARIANT(4, 8, 8, 1, 2, 4),  // 32 x 1008, 512 threads
     DEDISP_VARIANT(2, 4, 8, 2, 2, 2),  // 16 x 1008, 1024 threads
+    DEDISP_VARIANT(2, 8, 8, 1, 8, 1),  // 16 x 1008, 512 threads, 8 channels per stage (small delay spreads)
 };
 constexpr int kNumTiled = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -908,6 +914,13 @@ int variant_count() { return 1 + kNumTiled; }
 
 TileShape variant_shape(int v) { return kVariants[v - 1].shape; }
 
+int tiled_per_cu(dedisp_plan p, int v) {
+  if (v < 1 || v > kNumTiled) return 0;
+  const int runs = slot_runs(p, kVariants[v - 1]);
+  if (runs == 0) return 0;
+  return static_cast<int>((kMaxLds - 256) / (2 * static_cast<size_t>(kVariants[v - 1].cg) * runs * 1024));
+}
+
 bool variant_fits(dedisp_plan p, int v) {
   if (v == 0) return true;
   if (v < 0 || v > kNumTiled) return false;
@@ -915,7 +928,7 @@ bool variant_fits(dedisp_plan p, int v) {
 }
 
 int default_variant(dedisp_plan p) {
-  static const int order[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 10};
+  static const int order[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11};
   for (int v : order)
     if (v <= kNumTiled && variant_fits(p, v)) return v;
   return 0;
@@ -1180,9 +1193,12 @@ int prepare(dedisp_plan p, int v, int64_t nsamp) {
   return allow_large_lds(kVariants[v - 1].fn[p->dtype]);
 }
 
-const void* batch_kernel(int v) { return (v >= 1 && v <= kNumTiled) ? kVariants[v - 1].batch : nullptr; }
+const void* batch_kernel(int v, bool pairs) {
+  return (v >= 1 && v <= kNumTiled) ? kVariants[v - 1].batch[pairs ? 1 : 0] : nullptr;
+}
 
 const void* reset_kernel() { return reinterpret_cast<const void*>(&reset_counter); }
+int reset_kernel_threads() { return kBatchCounters; }
 
 }  // namespace dedisp
 

@@ -137,6 +137,49 @@ def test_batch_every_variant(dd):
         dd.dedisp_batch_destroy(batch)
 
 
+def test_batch_split_by_plan_variants(dd):
+    """Beams whose plans carry different variants (one tiled variant for most
+    of the work, others tiled differently or direct): split by the plans' own
+    variants, every beam equals its solo launch bit for bit, over replays."""
+    import torch
+    beams = small_beams(seed=9, nbeams=6)
+    data = make_inputs(beams)
+    plans = [dd.Plan.for_workload(w) for w in beams]
+    plans[0].variant = 1
+    plans[1].variant = 5
+    plans[2].variant = 1
+    plans[3].variant = 0
+    plans[4].variant = 11
+    ins = [to_device(x) for (_, _, x) in data]
+    stream = torch.cuda.current_stream()
+    solo = []
+    for p, w, xi in zip(plans, beams, ins):
+        o = alloc_out(w)
+        p.execute(xi, o, w.nsamp, stream)
+        solo.append(o)
+    torch.cuda.synchronize()
+    solo = [o.cpu().numpy().view(np.uint32) for o in solo]
+    batch = dd.dedisp_batch_create([p.handle for p in plans], [w.nsamp for w in beams])
+    try:
+        dd.dedisp_batch_set_variant(batch, 0)
+        for rep in range(3):
+            outs = [alloc_out(w) for w in beams]
+            dd.dedisp_batch_execute(batch, [t.data_ptr() for t in ins], [t.data_ptr() for t in outs], stream)
+            torch.cuda.synchronize()
+            for w, o, s in zip(beams, outs, solo):
+                assert np.array_equal(o.cpu().numpy().view(np.uint32), s), "beam %s replay %d" % (w.name, rep)
+        assert dd.dedisp_batch_get_variant(batch) >= 1
+        v, ms = dd.dedisp_batch_autotune(batch, [t.data_ptr() for t in ins], [t.data_ptr() for t in outs])
+        assert v >= 1 and ms > 0
+        outs = [alloc_out(w) for w in beams]
+        dd.dedisp_batch_execute(batch, [t.data_ptr() for t in ins], [t.data_ptr() for t in outs], stream)
+        torch.cuda.synchronize()
+        for w, o, s in zip(beams, outs, solo):
+            assert np.array_equal(o.cpu().numpy().view(np.uint32), s), "beam %s after autotune" % w.name
+    finally:
+        dd.dedisp_batch_destroy(batch)
+
+
 def test_batch_rejects_bad_args(dd):
     p = dd.Plan(8, 150.0, 0.5, 327.68e-6, [0.0, 1.0], "f32")
     with pytest.raises(dd.DedispError):
