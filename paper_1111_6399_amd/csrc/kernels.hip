@@ -796,7 +796,7 @@ __global__ __launch_bounds__(256) void widen_job_kernel(const WidenJob* __restri
 }
 
 // Persistent batch kernel: resident workgroups pull (beam, trial tile, time
-// tile) items from one atomic counter until none are left.  Items are
+// tile) items from atomic counters (one per XCD) until none are left.  Items are
 // numbered beam by beam, beams in order of decreasing cost per item (longest
 // items first), and inside a beam in the same groups as a single launch.  One
 // kernel per staging kind (its beams are all 8-bit, or all float and half),
