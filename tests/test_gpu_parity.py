@@ -81,6 +81,22 @@ def test_lofar_shape_reduced_time(dd, dtype):
             assert e.max() < REL_TOL
 
 
+def test_meerkat_block_tile_variants(dd):
+    """The MeerKAT-shaped block's full channel and trial grid (4096 x 4096,
+    uint8), 2100 output samples (two 1008-sample time tiles and a ragged
+    tail): the small-spread tile (16 trials x 1008, 8 channels a stage) and
+    the 8 x 2016 tile with 4 channels a stage equal the oracle on sampled
+    trials."""
+    w = wl.meerkat_block(nsamp=2100)
+    sh, m, x = make_case(w)
+    plan = dd.Plan.for_workload(w)
+    rows = np.unique(np.concatenate([np.arange(0, 4096, 97), [0, 1, 15, 16, 17, 4094, 4095]]))
+    want = oracle.dedisperse(x, sh, w.nsamp, rows=rows)
+    for v in (11, 5):
+        got = run(plan, x, w.nsamp, variant=v)[rows]
+        assert np.array_equal(got.astype(np.int64), want), "variant %d" % v
+
+
 def test_f16_error_against_float_data(dd):
     """Per-trial error of the half-precision path against the binary64 oracle on the
     original float32 data (quantisation included), reported, and the exact-input gate."""
