@@ -297,23 +297,27 @@ int dedisp_batch_execute(dedisp_batch batch, const void *const *ins, void *const
  * both are 0 before the first execute). */
 int dedisp_batch_info(dedisp_batch batch, int64_t *work_items, int *workgroups);
 
-/* Tile variant of the persistent kernel (>= 1; -1 if no beam runs in it).
- * Setting v >= 1 runs every beam that variant fits in the persistent kernel
- * (the rest on their own); setting 0 splits by each plan's own variant (the
- * persistent kernel takes the variant that carries the most work, the other
- * beams run on their own, each with its plan's variant).  Setting rebuilds
- * the graph on the next execute; it synchronises the batch's device. */
+/* Tile variant of the persistent kernel that carries the most work (>= 1; -1
+ * if no beam runs in one).  Setting v >= 1 runs every beam that variant fits
+ * in persistent kernels (the rest on their own); setting 0 splits by each
+ * plan's own variant (beams with a tiled variant in persistent kernels of
+ * that variant, the others on their own); setting -1 launches every beam on
+ * its own with its plan's variant, the launches captured in the graph.
+ * Setting rebuilds the graph on the next execute; it synchronises the
+ * batch's device. */
 int dedisp_batch_get_variant(dedisp_batch batch, int *variant);
 int dedisp_batch_set_variant(dedisp_batch batch, int variant);
 
 /* Time the batch with every tile variant that fits any of its beams; with
  * 8-bit and float beams mixed, also each variant for the 8-bit beams with the
  * float beams' held, then each for the float beams (the two kinds run as
- * separate persistent kernels); and the split that follows each plan's own
- * variant (set or tuned with dedisp_autotune).  Keeps the fastest;
- * best_variant is then the variant of the persistent kernel that carries the
- * most work.  Synchronises the stream.  The outputs are overwritten (with
- * correct results).  best_ms may be NULL. */
+ * separate persistent kernels); the split that follows each plan's own
+ * variant (set or tuned with dedisp_autotune); and every beam launched on its
+ * own with its plan's variant, the launches captured in the graph.  Keeps the
+ * fastest; best_variant is then the variant of the persistent kernel that
+ * carries the most work (-1 if the per-beam launches won).  Synchronises the
+ * stream.  The outputs are overwritten (with correct results).  best_ms may
+ * be NULL. */
 int dedisp_batch_autotune(dedisp_batch batch, const void *const *ins, void *const *outs, void *stream,
                           int *best_variant, double *best_ms);
 

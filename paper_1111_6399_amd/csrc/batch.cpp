@@ -211,6 +211,14 @@ bool assign_own(dedisp_batch b) {
   return !same;
 }
 
+// Every beam on its own with its plan's variant, the launches captured in the
+// graph (no persistent kernel).
+void assign_solo(dedisp_batch b) {
+  std::vector<int> tiled(b->nbeams, -1), solo_v(b->nbeams, 0);
+  for (int i = 0; i < b->nbeams; ++i) solo_v[i] = own_variant(b, i);
+  form_groups(b, tiled, solo_v);
+}
+
 // Variant that fits the most work of the batch (ties: library order).
 int pick_variant(dedisp_batch b) {
   int best = -1;
@@ -516,7 +524,7 @@ extern "C" int dedisp_batch_autotune(dedisp_batch b, const void* const* ins, voi
     return r;
   };
   int best = -1;
-  bool best_own = false;
+  bool best_own = false, best_solo = false;
   double best_t = 1e30;
   for (int v = 1; v < dedisp::variant_count() && st == DEDISP_OK; ++v) {
     bool any = false;
@@ -569,12 +577,26 @@ extern "C" int dedisp_batch_autotune(dedisp_batch b, const void* const* ins, voi
       }
     }
   }
+  if (st == DEDISP_OK) {
+    (void)hipStreamSynchronize(stream);
+    free_device(b);
+    assign_solo(b);
+    double t = 0.0;
+    st = time_split(&t);
+    if (st == DEDISP_OK && t < best_t) {
+      best_t = t;
+      best_solo = true;
+      best_own = kinds = false;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != DEDISP_OK) return st;
   (void)hipStreamSynchronize(stream);
   free_device(b);
-  if (best_own)
+  if (best_solo)
+    assign_solo(b);
+  else if (best_own)
     assign_own(b);
   else if (kinds)
     assign_kinds(b, best8, bestf);
@@ -592,13 +614,15 @@ extern "C" int dedisp_batch_get_variant(dedisp_batch b, int* variant) {
 }
 
 extern "C" int dedisp_batch_set_variant(dedisp_batch b, int variant) {
-  if (b == nullptr || variant < 0 || variant >= dedisp::variant_count()) return DEDISP_ERR_INVALID_ARG;
+  if (b == nullptr || variant < -1 || variant >= dedisp::variant_count()) return DEDISP_ERR_INVALID_ARG;
   int dev0 = -1;
   if (b->device >= 0 && hipGetDevice(&dev0) == hipSuccess) (void)hipSetDevice(b->device);
   if (b->device >= 0) (void)hipDeviceSynchronize();
   free_device(b);
   if (dev0 >= 0) (void)hipSetDevice(dev0);
-  if (variant == 0)
+  if (variant == -1)
+    assign_solo(b);
+  else if (variant == 0)
     (void)assign_own(b);
   else
     assign(b, variant);

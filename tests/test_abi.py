@@ -159,12 +159,15 @@ def test_batch_create_checks(dd):
     b = dd.dedisp_batch_create([p.handle, p.handle], [100, 200])
     assert dd.dedisp_batch_info(b) == (0, 0)
     assert dd.dedisp_batch_get_variant(b) >= 1
-    for bad in (-1, dd.dedisp_variant_count()):
+    for bad in (-2, dd.dedisp_variant_count()):
         with pytest.raises(dd.DedispError):
             dd.dedisp_batch_set_variant(b, bad)
     # 0: split by the plans' own variants (host bookkeeping only, no device work)
     dd.dedisp_batch_set_variant(b, 0)
     assert dd.dedisp_batch_get_variant(b) >= 1
+    # -1: every beam on its own
+    dd.dedisp_batch_set_variant(b, -1)
+    assert dd.dedisp_batch_get_variant(b) == -1
     dd.dedisp_batch_destroy(b)
 
 

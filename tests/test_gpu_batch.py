@@ -132,7 +132,10 @@ def test_batch_every_variant(dd):
                     assert np.array_equal(a, b), "variant %d" % v
         tune_outs = [alloc_out(w) for w in beams]
         v, ms = dd.dedisp_batch_autotune(batch, [t.data_ptr() for t in ins], [t.data_ptr() for t in tune_outs])
-        assert v >= 1 and ms > 0
+        assert (v >= 1 or v == -1) and ms > 0
+        torch.cuda.synchronize()
+        for a, o in zip(ref, tune_outs):
+            assert np.array_equal(a, o.cpu().numpy().view(np.uint32)), "autotuned split"
     finally:
         dd.dedisp_batch_destroy(batch)
 
@@ -169,8 +172,17 @@ def test_batch_split_by_plan_variants(dd):
             for w, o, s in zip(beams, outs, solo):
                 assert np.array_equal(o.cpu().numpy().view(np.uint32), s), "beam %s replay %d" % (w.name, rep)
         assert dd.dedisp_batch_get_variant(batch) >= 1
+        # every beam launched on its own inside the graph
+        dd.dedisp_batch_set_variant(batch, -1)
+        assert dd.dedisp_batch_get_variant(batch) == -1
+        for rep in range(2):
+            outs = [alloc_out(w) for w in beams]
+            dd.dedisp_batch_execute(batch, [t.data_ptr() for t in ins], [t.data_ptr() for t in outs], stream)
+            torch.cuda.synchronize()
+            for w, o, s in zip(beams, outs, solo):
+                assert np.array_equal(o.cpu().numpy().view(np.uint32), s), "beam %s per-beam replay %d" % (w.name, rep)
         v, ms = dd.dedisp_batch_autotune(batch, [t.data_ptr() for t in ins], [t.data_ptr() for t in outs])
-        assert v >= 1 and ms > 0
+        assert (v >= 1 or v == -1) and ms > 0
         outs = [alloc_out(w) for w in beams]
         dd.dedisp_batch_execute(batch, [t.data_ptr() for t in ins], [t.data_ptr() for t in outs], stream)
         torch.cuda.synchronize()
