@@ -29,7 +29,8 @@ namespace {
 
 constexpr int kDetThreads = 256;
 constexpr int kDetChunk = 4096;  // boxcar start times per LDS chunk
-constexpr int kUnroll = 8;       // global loads in flight per thread
+constexpr int kUnroll = 8;       // global loads in flight per thread (moments pass)
+constexpr int kChunkUnroll = 18; // global loads in flight per thread (chunk loads: one round for 4096 + 511)
 
 // The S/N of a boxcar of width 2^k with sum b is (b - snr_base) * snr_scale.
 __device__ __forceinline__ double snr_base(int k, double mean) { return static_cast<double>(1 << k) * mean; }
@@ -155,21 +156,21 @@ __global__ __launch_bounds__(kDetThreads) void detect_rows(const T* __restrict__
   double* P = sh;
   for (int64_t t0 = 0; t0 < nsamp; t0 += kDetChunk) {
     const int L = static_cast<int>(min(static_cast<int64_t>(span), nsamp - t0));  // samples held
-    for (int i = tid; i < L; i += kUnroll * kDetThreads) {
-      double v[kUnroll];
+    for (int i = tid; i < L; i += kChunkUnroll * kDetThreads) {
+      T v[kChunkUnroll];  // raw samples, converted as they are stored
 #pragma unroll
-      for (int j = 0; j < kUnroll; ++j) {
+      for (int j = 0; j < kChunkUnroll; ++j) {
         const int u = i + j * kDetThreads;
-        v[j] = static_cast<double>(row[t0 + (u < L ? u : L - 1)]);
+        v[j] = row[t0 + (u < L ? u : L - 1)];
       }
 #pragma unroll
-      for (int j = 0; j < kUnroll; ++j)
-        if (i + j * kDetThreads < L) P[i + j * kDetThreads] = v[j];
-      if constexpr (kSums) {
-        // each sample once: the chunk's own samples, not the overlap into the next
-#pragma unroll
-        for (int j = 0; j < kUnroll; ++j) {
-          const double e = i + j * kDetThreads < min(L, kDetChunk) ? v[j] - k0 : 0.0;
+      for (int j = 0; j < kChunkUnroll; ++j) {
+        const int u = i + j * kDetThreads;
+        const double x = static_cast<double>(v[j]);
+        if (u < L) P[u] = x;
+        if constexpr (kSums) {
+          // each sample once: the chunk's own samples, not the overlap into the next
+          const double e = u < min(L, kDetChunk) ? x - k0 : 0.0;
           s1 += e;
           s2 += e * e;
         }
