@@ -1140,11 +1140,12 @@ int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, T
   const int64_t n_t_tiles = (nsamp + var.shape.samples() - 1) / var.shape.samples();
   if (n_t_tiles > INT32_MAX / 64) return DEDISP_ERR_INVALID_ARG;
   a.n_t_tiles = static_cast<int>(n_t_tiles);
-  // groups of up to 16 trial tiles x 1 time tile (16-bit pair staging) or x 2
-  // (float staging): measured against 8 x 4, 4 x 8, 2 x 16, 32 x 1, 64 x 1 and
-  // others, consecutive trial tiles in one XCD were fastest for every variant
-  a.gd = std::min(16, a.n_dm_tiles);
-  a.gt = std::min(p->dtype == DEDISP_U8 ? 1 : 2, a.n_t_tiles);
+  // groups of up to 16 trial tiles x 1 time tile (16-bit pair staging) or
+  // 8 x 3 (float staging), the fastest of a sweep of group shapes on the
+  // LOFAR-shaped and MeerKAT-shaped workloads
+  const bool pairs = p->dtype == DEDISP_U8;
+  a.gd = std::min(pairs ? 16 : 8, a.n_dm_tiles);
+  a.gt = std::min(pairs ? 1 : 3, a.n_t_tiles);
   a.n_dm_groups = (a.n_dm_tiles + a.gd - 1) / a.gd;
   const int64_t n_groups = static_cast<int64_t>(a.n_dm_groups) * ((a.n_t_tiles + a.gt - 1) / a.gt);
   // a multiple of 8 groups, so that every XCD's run of blocks is whole groups
