@@ -360,14 +360,14 @@ __device__ __forceinline__ void lds_dma_runs(uint32_t lds, uint32_t voff, const 
                  "buffer_load_dwordx4 %[vo], %[rs], 0 offen lds"
                  :
                  : [lds] "s"(lds), [vo] "v"(voff), [rs] "s"(rs)
-                 : "memory");
+                 : "memory", "m0");
   else if constexpr (K == 2)
     asm volatile("s_mov_b32 m0, %[lds]\n\ts_nop 0\n\t"
                  "buffer_load_dwordx4 %[vo], %[rs], 0 offen lds\n\t"
                  "buffer_load_dwordx4 %[vo], %[rs], 0 offen offset:1024 lds"
                  :
                  : [lds] "s"(lds), [vo] "v"(voff), [rs] "s"(rs)
-                 : "memory");
+                 : "memory", "m0");
   else if constexpr (K == 3)
     asm volatile("s_mov_b32 m0, %[lds]\n\ts_nop 0\n\t"
                  "buffer_load_dwordx4 %[vo], %[rs], 0 offen lds\n\t"
@@ -375,7 +375,7 @@ __device__ __forceinline__ void lds_dma_runs(uint32_t lds, uint32_t voff, const 
                  "buffer_load_dwordx4 %[vo], %[rs], 0 offen offset:2048 lds"
                  :
                  : [lds] "s"(lds), [vo] "v"(voff), [rs] "s"(rs)
-                 : "memory");
+                 : "memory", "m0");
   else
     asm volatile("s_mov_b32 m0, %[lds]\n\ts_nop 0\n\t"
                  "buffer_load_dwordx4 %[vo], %[rs], 0 offen lds\n\t"
@@ -384,7 +384,7 @@ __device__ __forceinline__ void lds_dma_runs(uint32_t lds, uint32_t voff, const 
                  "buffer_load_dwordx4 %[vo], %[rs], 0 offen offset:3072 lds"
                  :
                  : [lds] "s"(lds), [vo] "v"(voff), [rs] "s"(rs)
-                 : "memory");
+                 : "memory", "m0");
 }
 
 // LDS read address of a (channel, trial) block: the lane's base plus the

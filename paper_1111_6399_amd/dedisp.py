@@ -332,6 +332,35 @@ def dedisp_server_destroy(server: int) -> None:
 
 # ------------------------------------------------------- convenience layer
 
+# Element type names (torch dtype names) of a plan's input and output, by dtype code.
+_IN_DTYPES = {DEDISP_U8: "uint8", DEDISP_F16: "float16", DEDISP_F32: "float32"}
+_OUT_DTYPES = {DEDISP_U8: "int32", DEDISP_F16: "float32", DEDISP_F32: "float32"}
+
+
+def device_address(buf, dtype_name: str, min_numel: int, what: str) -> int:
+    """Address of a device buffer.  A tensor (anything with ``data_ptr()``) must
+    be on the GPU, contiguous, of element type ``dtype_name`` and hold at least
+    ``min_numel`` elements, else DedispError(INVALID_ARG) is raised before any
+    library call; a plain integer is taken as an address as it is."""
+    if not hasattr(buf, "data_ptr"):
+        return int(buf)
+    problems = []
+    dev = getattr(buf, "device", None)
+    if dev is not None and getattr(dev, "type", "cuda") != "cuda":
+        problems.append("not on the GPU (%s)" % dev)
+    if hasattr(buf, "is_contiguous") and not buf.is_contiguous():
+        problems.append("not contiguous")
+    dt = str(getattr(buf, "dtype", dtype_name)).replace("torch.", "")
+    if dt != dtype_name:
+        problems.append("element type %s, expected %s" % (dt, dtype_name))
+    n = int(buf.numel()) if hasattr(buf, "numel") else min_numel
+    if n < min_numel:
+        problems.append("%d elements, expected at least %d" % (n, min_numel))
+    if problems:
+        raise DedispError(DEDISP_ERR_INVALID_ARG, "%s buffer: %s" % (what, "; ".join(problems)))
+    return int(buf.data_ptr())
+
+
 class Plan:
     """Owning wrapper of a plan handle."""
 
@@ -356,9 +385,14 @@ class Plan:
         dedisp_plan_set_variant(self.handle, v)
 
     def execute(self, inp, out, nsamp: int, stream=None) -> None:
-        """``inp``/``out`` are device tensors (anything with ``data_ptr()``) or raw addresses."""
-        ip = inp.data_ptr() if hasattr(inp, "data_ptr") else int(inp)
-        op = out.data_ptr() if hasattr(out, "data_ptr") else int(out)
+        """``inp``/``out`` are device tensors or raw addresses.  Tensors are
+        checked first (on the GPU, contiguous, element type of the plan, at
+        least ``nchans*(nsamp+max_shift)`` input and ``ndm*nsamp`` output
+        elements), since the library cannot see the size of an allocation."""
+        nsamp = int(nsamp)
+        n = max(nsamp, 0)  # the library itself rejects a negative count and does nothing for 0
+        ip = device_address(inp, _IN_DTYPES[self.dtype_code], self.nchans * (n + self.max_shift) if n else 0, "input")
+        op = device_address(out, _OUT_DTYPES[self.dtype_code], self.ndm * n, "output")
         dedisp_execute(self.handle, ip, op, nsamp, stream)
 
     def close(self) -> None:

@@ -296,3 +296,66 @@ def test_execute_cpu_argument_checks(dd):
     assert f(plan.handle, 16, 16, -1, 0, None) == dd.DEDISP_ERR_INVALID_ARG
     assert f(plan.handle, 16, 16, 10, -2, None) == dd.DEDISP_ERR_INVALID_ARG
     assert f(plan.handle, None, None, 0, 0, None) == dd.DEDISP_OK  # nothing to do
+
+
+class _FakeDeviceTensor:
+    """Stands in for a device tensor: only what the binding's checks read."""
+
+    class _Dev:
+        type = "cuda"
+
+    def __init__(self, dtype, numel, contiguous=True):
+        self.dtype, self._n, self._c, self.device = dtype, numel, contiguous, self._Dev()
+
+    def numel(self):
+        return self._n
+
+    def is_contiguous(self):
+        return self._c
+
+    def data_ptr(self):
+        return 0x1000
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f16", "f32"])
+def test_execute_checks_tensors_before_the_library(dd, dtype, monkeypatch):
+    """Plan.execute rejects a buffer of the wrong element type, too few
+    elements, non-contiguous or on the host, before any call into the library
+    (whose kernels cannot see the size of an allocation)."""
+    import torch
+    p = dd.Plan(8, 150.0, 0.5, 327.68e-6, [0.0, 1.0, 2.0], dtype)
+    n = 100
+    nin = 8 * (n + p.max_shift)
+    tin = {"u8": torch.uint8, "f16": torch.float16, "f32": torch.float32}[dtype]
+    tout = torch.int32 if dtype == "u8" else torch.float32
+    wrong_in = torch.float32 if dtype != "f32" else torch.uint8
+    wrong_out = torch.float32 if dtype == "u8" else torch.int32
+    good_out = _FakeDeviceTensor(tout, 3 * n)
+    cases = [
+        (_FakeDeviceTensor(wrong_in, nin), good_out),                 # element type of the input
+        (_FakeDeviceTensor(tin, nin - 1), good_out),                  # one input element short
+        (_FakeDeviceTensor(tin, nin, contiguous=False), good_out),    # strided view
+        (torch.zeros(nin, dtype=tin), good_out),                      # host tensor
+        (_FakeDeviceTensor(tin, nin), _FakeDeviceTensor(wrong_out, 3 * n)),
+        (_FakeDeviceTensor(tin, nin), _FakeDeviceTensor(tout, 3 * n - 1)),
+    ]
+    def no_call(*a, **k):
+        raise AssertionError("the library was called with a rejected buffer")
+
+    monkeypatch.setattr(dd, "dedisp_execute", no_call)
+    for xin, out in cases:
+        with pytest.raises(dd.DedispError) as e:
+            p.execute(xin, out, n)
+        assert e.value.status == dd.DEDISP_ERR_INVALID_ARG
+
+
+def test_library_rounds_exact_ties_half_up(dd):
+    """The library's delay table at binary64 products that are exactly n + 1/2
+    (gives n + 1) or the double just below (gives n): tests/golden/tie_pins.json."""
+    import json
+    doc = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "tie_pins.json")))
+    for case in doc["cases"]:
+        b = doc["bands"][case["band"]]
+        c = case["channel"]
+        p = dd.Plan(c + 1, b["f_top"], b["df"], b["tsamp"], [float.fromhex(case["dm"])], "u8")
+        assert p.shift_table()[c, 0] == case["value"], case

@@ -444,3 +444,52 @@ def test_corner_turn_definition():
     for t in range(7):
         for c in range(5):
             assert y[c, t] == x[t, c] and r[4 - c, t] == x[t, c]
+
+
+# ------------------------------------------------------------------ rounding at the tie itself
+
+TIES = os.path.join(os.path.dirname(__file__), "golden", "tie_pins.json")
+
+
+def tie_cases():
+    doc = json.load(open(TIES))
+    for case in doc["cases"]:
+        yield doc["bands"][case["band"]], case
+
+
+def test_tie_fixture_products_are_exact():
+    """Each stored DM really puts the binary64 product DM*k_c on the stated
+    value (exact rational product, rounded once), with k_c evaluated in the
+    table's binary64 order."""
+    n = 0
+    for b, case in tie_cases():
+        f = b["f_top"] - float(case["channel"]) * b["df"]
+        k = 4148.808 * (1.0 / (f * f) - 1.0 / (b["f_top"] * b["f_top"])) / b["tsamp"]
+        dm, x = float.fromhex(case["dm"]), float.fromhex(case["x"])
+        assert float(Fraction(dm) * Fraction(k)) == x == dm * k
+        if case["kind"] == "tie":
+            assert x - np.floor(x) == 0.5
+        else:
+            assert x < np.floor(x) + 0.5 and np.nextafter(x, np.inf) == np.floor(x) + 0.5
+        n += 1
+    assert n >= 12
+
+
+def test_tie_pins_tell_rounding_rules_apart():
+    """The stored cases separate round half up from the two plausible slips:
+    half-to-even (numpy rint, Python round) and floor(x + 1/2)."""
+    xs = np.array([float.fromhex(c["x"]) for _, c in tie_cases()])
+    want = np.array([c["value"] for _, c in tie_cases()])
+    half_up = np.floor(xs) + ((xs - np.floor(xs)) >= 0.5)
+    assert np.array_equal(half_up, want)
+    assert not np.array_equal(np.rint(xs), want)
+    assert not np.array_equal(np.floor(xs + 0.5), want)
+
+
+def test_oracle_rounds_exact_ties_half_up():
+    """Reading of the delay rounding (round half up on the binary64 product):
+    an exact n + 1/2 gives n + 1, the double just below it gives n."""
+    for b, case in tie_cases():
+        c = case["channel"]
+        sh, _ = oracle.shift_table(c + 1, b["f_top"], b["df"], b["tsamp"], np.array([float.fromhex(case["dm"])]))
+        assert sh[c, 0] == case["value"], case
