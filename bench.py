@@ -24,17 +24,27 @@ sys.path.insert(0, ROOT)
 METRIC = "DM·chan·samples/s + real-time factor on 1 GPU; p50/p99 block latency served"
 UNIT = "DM·chan·samples/s"
 
-# MI355X: 256 CUs x 4 SIMDs x 32 lanes per clock for a full-rate 32-bit VALU op
-# (v_add_f32 / v_add_u32) at 2.4 GHz = 78.6e12 adds/s, i.e. the published
-# 157.3 TFLOP/s fp32 vector peak counted as one add per FMA slot.
+# MI355X published float32 vector peak, 157.3 TFLOP/s, counted as one add per
+# FMA slot: 256 CUs x 2.4 GHz x 128 lane-adds per clock = 78.6e12 adds/s.
+# Reaching it takes packed float32 instructions (two adds a lane), which this
+# build does not use; without them the same units give half of it, 39.3e12
+# (64 lane-adds per CU and clock).  Both fractions are reported.
 ALU_PEAK_TADDS = 256 * 128 * 2.4e9 / 1e12
+ALU_UNPACKED_TADDS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
-# LDS read rate of the accumulation's access pattern (64-bit reads, 512
-# contiguous bytes per wave read), measured on MI355X: about 205 bytes per
-# clock per CU.
-LDS_READ_TBS = 205 * 256 * 2.4e9 / 1e12
+# LDS: one ds_read_b64 (512 bytes a wave) keeps a CU's LDS busy for 2 clocks
+# (SQ_LDS_IDX_ACTIVE = 2 x SQ_INSTS_LDS on the tile kernels), i.e. 256 bytes
+# per clock per CU, 157 TB/s for the chip.  The accumulation reads 4 bytes per
+# float add and 2 bytes per add of 16-bit staged samples (half, or two 8-bit
+# samples per 32-bit add), times 64/63 for the halo lane.
+LDS_PEAK_TBS = 256 * 256 * 2.4e9 / 1e12
+# The paper's own estimate for its GPU kernel: about 40-50 % of the peak of an
+# NVIDIA Fermi GPU (section "Conclusions"; "peak" not defined there).
+PAPER_CONTEXT = ("paper: GPU kernel estimated at ~40-50% of peak on an NVIDIA Fermi GPU (section Conclusions); "
+                 "CPU comparison on Sandy Bridge / Xeon with vector intrinsics; no absolute rates in the text")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1111_6399_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters.json")
 
 
 def kernel_sha() -> str:
@@ -42,18 +52,41 @@ def kernel_sha() -> str:
     return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
 
 
-def measured_traffic(workload_name: str, variant: int):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    FETCH_SIZE/WRITE_SIZE summary (scaled by a plain copy), or None when the
-    kernel source or variant differs from the one the counters were taken on."""
+def _record(path: str, key: str, variant: int):
     try:
-        rec = json.load(open(TRAFFIC_FILE)).get("%s/v%d" % (workload_name, variant))
+        rec = json.load(open(path)).get(key)
     except (OSError, ValueError):
         return None
     if not rec or rec.get("kernel_sha256") != kernel_sha() or rec.get("variant") != variant:
         return None
+    return rec
+
+
+def measured_traffic(workload_name: str, variant: int):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary (scaled by a plain copy), or None when the
+    kernel source or variant differs from the one the counters were taken on."""
+    rec = _record(TRAFFIC_FILE, "%s/v%d" % (workload_name, variant), variant)
+    if rec is None:
+        return None
     return {"bytes": rec["fetch_bytes"] + rec["write_bytes"], "fetch_bytes": rec["fetch_bytes"],
             "write_bytes": rec["write_bytes"], "source": rec.get("source")}
+
+
+def measured_counters(workload_name: str, variant: int):
+    """Instruction and LDS counters per launch of the dominant kernel from the
+    committed rocprofv3 summary, or None when the kernel changed since."""
+    return _record(COUNTERS_FILE, "%s/v%d" % (workload_name, variant), variant)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def log(msg: str) -> None:
@@ -121,6 +154,7 @@ def cpu_baseline(x, shift, nsamp, ndm, nchans, target_s=12.0):
         if dt >= target_s or reps >= 50:
             break
     return {"value": reps * n * nchans * nsamp / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": "%d x (%d of %d trials x %d output samples x %d channels), %.1f s"
                       % (reps, n, ndm, nsamp, nchans, dt)}
 
@@ -140,7 +174,7 @@ def cpu_vectorised(plan, x, nsamp, ndm, nchans, target_s=8.0):
         dt = time.perf_counter() - t
         if dt >= 0.5 * target_s or reps >= 20:
             break
-    return {"value": reps * float(ndm) * nchans * nsamp / dt, "unit": UNIT, "cores": threads,
+    return {"value": reps * float(ndm) * nchans * nsamp / dt, "unit": UNIT, "cores": threads, "cpu_model": cpu_model(),
             "kind": "vectorised host search (dedisp_execute_cpu)", "isa": {2: "avx512", 1: "avx2", 0: "scalar"}[isa],
             "sample": "%d x the whole workload, %.1f s" % (reps, dt)}
 
@@ -257,38 +291,44 @@ def run_batch(args) -> dict:
     }
 
 
-def run_served(args) -> dict:
+P99_TARGET_S = 0.5  # served latency target: a quarter of a 2.1 s MeerKAT block
+
+
+def served_compare(nbeams, rate_x, warmup_s, duration, inflight=8, budget_gb=128.0, pool_n=4, max_backlog=256,
+                   variant=-1, plan=None):
     """64 MeerKAT-shaped beams (4096 channels, 4096 trials 0-2047.5, uint8),
     blocks of 32768 samples arriving as independent per-beam Poisson
-    processes at ``--rate`` times real time in aggregate.  Latency runs from a
+    processes at rate_x times real time in aggregate.  Latency runs from a
     block's scheduled arrival (block already in pinned host memory) to its
     output being complete on the device.  The same arrival schedule is then
     replayed through the plain form: one FIFO, one stream, each block copied
-    behind its beam's history and launched on its own."""
+    behind its beam's history and launched on its own.  Returns (served,
+    plain, plan)."""
     import torch
 
     from paper_1111_6399_amd import dedisp as dd
     from paper_1111_6399_amd import workloads as wl
 
     dev = torch.device("cuda:0")
-    nbeams, B = args.beams, 32768
+    B = 32768
     w = wl.meerkat_block(B)
-    plan = dd.Plan.for_workload(w)
+    if plan is None:
+        plan = dd.Plan.for_workload(w)
+        if variant >= 0:
+            plan.variant = variant
+        else:
+            v, ms = dd.dedisp_autotune(plan.handle, B)
+            log("autotune on one block: variant %d, %.3f ms" % (v, ms))
     m = plan.max_shift
     nch, ndm = w.band.nchans, w.ndm
     block_s = B * w.band.tsamp
     work = float(ndm) * nch * B
-    if args.variant >= 0:
-        plan.variant = args.variant
-    else:
-        v, ms = dd.dedisp_autotune(plan.handle, B)
-        log("autotune on one block: variant %d, %.3f ms" % (v, ms))
 
     # a pool of distinct pinned blocks, cycled through by (beam, block)
-    pool = [torch.from_numpy(wl.stream_block(5, k, 0, nch, B)).pin_memory() for k in range(args.pool)]
+    pool = [torch.from_numpy(wl.stream_block(5, k, 0, nch, B)).pin_memory() for k in range(pool_n)]
     rng = np.random.default_rng(5)
-    rate = args.rate / block_s  # per beam, blocks/s
-    horizon = args.warmup_s + args.duration
+    rate = rate_x / block_s  # per beam, blocks/s
+    horizon = warmup_s + duration
     arrivals = []
     for b in range(nbeams):
         t, k = 0.0, 0
@@ -299,8 +339,8 @@ def run_served(args) -> dict:
             arrivals.append((t, b, k))
             k += 1
     arrivals.sort()
-    log("served: %d beams, %d blocks over %.0f s (offered %.1f blocks/s = %.3g adds/s)"
-        % (nbeams, len(arrivals), horizon, len(arrivals) / horizon, work * len(arrivals) / horizon))
+    log("served at %.2fx real time: %d beams, %d blocks over %.0f s (offered %.1f blocks/s = %.3g adds/s)"
+        % (rate_x, nbeams, len(arrivals), horizon, len(arrivals) / horizon, work * len(arrivals) / horizon))
 
     def replay(submit, poll_done, nslots, label):
         """Drive one arrival schedule; submit(beam, blk, out) -> handle or None;
@@ -310,7 +350,7 @@ def run_served(args) -> dict:
         free = list(range(nslots))
         backlog, running, lat, sub_s = [], [], [], []
         t_start = time.perf_counter() + 0.05
-        i, max_backlog, overload = 0, 0, False
+        i, max_bl, overload = 0, 0, False
         first_done = last_done = None
         next_report = 15.0
         while i < len(arrivals) or backlog or running:
@@ -322,8 +362,8 @@ def run_served(args) -> dict:
             while i < len(arrivals) and arrivals[i][0] <= now:
                 backlog.append(arrivals[i])
                 i += 1
-            max_backlog = max(max_backlog, len(backlog))
-            if len(backlog) > args.max_backlog and not overload:
+            max_bl = max(max_bl, len(backlog))
+            if len(backlog) > max_backlog and not overload:
                 # the device cannot keep up with the offered load: stop taking
                 # arrivals, finish what was admitted, report the overload
                 overload = True
@@ -336,7 +376,7 @@ def run_served(args) -> dict:
                     tdone = time.perf_counter() - t_start
                     running.remove(r)
                     free.append(slot)
-                    if arr[0] >= args.warmup_s:
+                    if arr[0] >= warmup_s:
                         lat.append(tdone - arr[0])
                         first_done = tdone if first_done is None else first_done
                         last_done = tdone
@@ -356,7 +396,7 @@ def run_served(args) -> dict:
             if not progressed:
                 time.sleep(0.0002)
         del outs
-        return np.array(lat), (first_done, last_done), (max_backlog, overload, np.array(sub_s))
+        return np.array(lat), (first_done, last_done), (max_bl, overload, np.array(sub_s))
 
     def summary(lat, span, backlog, label):
         n = lat.size
@@ -368,10 +408,12 @@ def run_served(args) -> dict:
             "submit call %.2f ms mean %.2f ms max%s"
             % (label, n, 1e3 * (p50 or 0), 1e3 * (p99 or 0), thr or 0, backlog[0], 1e3 * (sub_mean or 0),
                1e3 * (sub_max or 0), " (OVERLOADED: arrivals stopped)" if backlog[1] else ""))
-        return {"blocks": n, "p50_s": p50, "p99_s": p99, "value": thr, "max_backlog": backlog[0],
-                "overloaded": backlog[1], "submit_mean_s": sub_mean, "submit_max_s": sub_max}
+        sustained = bool(n > 1 and not backlog[1] and p99 is not None and p99 <= P99_TARGET_S)
+        return {"rate_x_realtime": rate_x, "blocks": n, "p50_s": p50, "p99_s": p99, "value": thr,
+                "max_backlog": backlog[0], "overloaded": backlog[1], "sustained_at_p99_target": sustained,
+                "submit_mean_s": sub_mean, "submit_max_s": sub_max}
 
-    server = dd.dedisp_server_create(int(args.budget_gb * (1 << 30)), args.inflight)
+    server = dd.dedisp_server_create(int(budget_gb * (1 << 30)), inflight)
     try:
         bids = [dd.dedisp_server_add_beam(server, plan.handle, B) for _ in range(nbeams)]
 
@@ -381,7 +423,7 @@ def run_served(args) -> dict:
         def s_poll(tk):
             return dd.dedisp_poll(server, tk)[0]
 
-        lat, span, backlog = replay(s_submit, s_poll, args.inflight, "served")
+        lat, span, backlog = replay(s_submit, s_poll, inflight, "served")
         dd.dedisp_server_drain(server)
         p50s, p99s, rate_s = dd.dedisp_server_stats(server)
     finally:
@@ -411,18 +453,41 @@ def run_served(args) -> dict:
     torch.cuda.synchronize()
     plain = summary(lat, span, backlog, "plain FIFO")
     hist.clear()
+    del pool
+    torch.cuda.empty_cache()
+    return served, plain, plan
 
-    value = served["value"] or 0.0
+
+def run_served(args) -> dict:
+    """The served MeerKAT stream at each rate of --rates (x real time): the
+    server and the plain FIFO on the same arrival schedule, p50/p99 latency
+    and throughput, and the highest rate each form sustains with p99 within
+    P99_TARGET_S."""
+    rates = [float(r) for r in args.rates.split(",")] if args.rates else [args.rate]
+    rows, plan = [], None
+    for r in rates:
+        served, plain, plan = served_compare(args.beams, r, args.warmup_s, args.duration, args.inflight,
+                                             args.budget_gb, args.pool, args.max_backlog, args.variant, plan)
+        rows.append({"rate_x_realtime": r, "served": served, "plain_fifo": plain})
+    best = {form: max([row["rate_x_realtime"] for row in rows if row[form]["sustained_at_p99_target"]],
+                      default=None) for form in ("served", "plain_fifo")}
+    log("highest rate sustained with p99 <= %.0f ms: served %s, plain %s"
+        % (1e3 * P99_TARGET_S, best["served"], best["plain_fifo"]))
+    top = rows[0]["served"]
+    from paper_1111_6399_amd import workloads as wl
+    w = wl.meerkat_block(32768)
+    work = float(w.ndm) * w.band.nchans * 32768
+    value = top["value"] or 0.0
     achieved = value / 1e12
     return {
-        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": served["blocks"],
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": top["blocks"],
         "warmup": args.warmup_s, "ms_per_step": None if not value else work / value * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-        "config": {"workload": "served-meerkat", "nbeams": nbeams, "block": B, "ndm": ndm, "nchans": nch,
-                   "max_shift": m, "rate_x_realtime": args.rate, "duration_s": args.duration,
-                   "inflight": args.inflight, "variant": plan.variant},
-        "served": served, "plain_fifo": plain,
-        "rtf": None if not value else value / work * block_s,
+        "config": {"workload": "served-meerkat", "nbeams": args.beams, "block": 32768, "ndm": w.ndm,
+                   "nchans": w.band.nchans, "max_shift": plan.max_shift, "rates_x_realtime": rates,
+                   "duration_s": args.duration, "inflight": args.inflight, "variant": plan.variant},
+        "p99_target_s": P99_TARGET_S, "sweep": rows, "highest_sustained_rate_x": best,
+        "rtf": None if not value else value / work * 32768 * w.band.tsamp,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TADDS, "unit": "Tadd/s",
                      "frac": achieved / ALU_PEAK_TADDS, "traffic": None},
     }
@@ -572,18 +637,29 @@ def run_fig4(args) -> dict:
 
 
 def roofline(w, adds, alg_bytes, kernel_ms, variant) -> dict:
-    """Achieved add rate of the timed launch (HIP events on its stream) against
-    the ALU add peak, with the LDS-read ceiling the accumulation also meets
-    (4 bytes per float add, 2 per 8-bit add) and the HBM traffic."""
+    """Achieved add rate of the timed launches (median of HIP events on their
+    stream) against the ALU add peak (and its unpacked half), with the LDS
+    read rate the accumulation needs (and the one the counters measured) and
+    the HBM traffic from the committed counters."""
     achieved = adds / (kernel_ms * 1e-3) / 1e12
-    lds_bytes_per_add = (2.0 if w.dtype == "u8" else 4.0) * 64.0 / 63.0
+    lds_bytes_per_add = (4.0 if w.dtype == "f32" else 2.0) * 64.0 / 63.0
     lds_tbs = achieved * lds_bytes_per_add
     tr = measured_traffic(w.name, variant)
+    ctr = measured_counters(w.name, variant)
+    lds = {"model_TBps": lds_tbs, "peak_TBps": LDS_PEAK_TBS, "model_frac": lds_tbs / LDS_PEAK_TBS,
+           "bytes_per_add": lds_bytes_per_add}
+    if ctr is not None:
+        # bytes the counters saw per launch, over this run's median launch time
+        meas = ctr["lds_read_bytes"] / (kernel_ms * 1e-3) / 1e12
+        lds.update({"measured_TBps": meas, "measured_frac": meas / LDS_PEAK_TBS, "counters": ctr.get("source")})
     return {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TADDS, "unit": "Tadd/s",
-            "frac": achieved / ALU_PEAK_TADDS, "traffic": None if tr is None else tr["bytes"],
-            "traffic_detail": tr, "kernel_ms": kernel_ms, "alg_bytes": alg_bytes,
-            "hbm_alg_GBps": alg_bytes / (kernel_ms * 1e-3) / 1e9,
-            "lds_read_TBps": lds_tbs, "lds_read_peak_TBps": LDS_READ_TBS, "lds_frac": lds_tbs / LDS_READ_TBS}
+            "frac": achieved / ALU_PEAK_TADDS, "frac_unpacked": achieved / ALU_UNPACKED_TADDS,
+            "traffic": None if tr is None else tr["bytes"],
+            "traffic_detail": tr, "kernel_ms": kernel_ms, "kernel_ms_stat": "median", "alg_bytes": alg_bytes,
+            "traffic_over_alg": None if tr is None else tr["bytes"] / alg_bytes,
+            "hbm_alg_GBps": alg_bytes / (kernel_ms * 1e-3) / 1e9, "lds": lds,
+            "counters": None if ctr is None else {k: v for k, v in ctr.items() if k.startswith(("SQ_", "per_"))},
+            "context": PAPER_CONTEXT}
 
 
 def main() -> int:
@@ -596,6 +672,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--beams", type=int, default=64, help="served: number of beams")
     ap.add_argument("--rate", type=float, default=1.5, help="served: aggregate arrival rate, x real time per beam")
+    ap.add_argument("--rates", default="", help="served: comma-separated rates to sweep (x real time)")
+    ap.add_argument("--no-served", action="store_true", help="skip the served leg of the default workload")
+    ap.add_argument("--served-duration", type=float, default=20.0, help="served leg: measured seconds")
     ap.add_argument("--duration", type=float, default=60.0, help="served: measured seconds after the warm-up")
     ap.add_argument("--warmup-s", type=float, default=10.0, help="served: warm-up seconds")
     ap.add_argument("--inflight", type=int, default=8, help="served: requests in flight")
@@ -659,16 +738,19 @@ def main() -> int:
     wall = time.perf_counter() - t0
     kms = [a.elapsed_time(bb) for a, bb in ev]
     ms_per_step = wall * 1e3 / args.steps
-    kernel_ms = float(np.mean(kms))
-    log("timed %d steps: %.3f ms/step wall, kernel %.3f ms (min %.3f)" % (args.steps, ms_per_step, kernel_ms,
-                                                                          min(kms)))
+    kernel_ms = float(np.median(kms))
+    log("timed %d steps: %.3f ms/step wall, kernel %.3f ms median (min %.3f, mean %.3f)"
+        % (args.steps, ms_per_step, kernel_ms, min(kms), float(np.mean(kms))))
 
     adds = float(w.ndm) * b.nchans * w.nsamp
     value = adds / (ms_per_step * 1e-3)
     rtf = w.nsamp * b.tsamp / (ms_per_step * 1e-3)
     esize = x.itemsize
-    alg_bytes = (b.nchans * (w.nsamp + plan.max_shift) * esize + w.ndm * w.nsamp * 4
-                 + b.nchans * w.ndm * 4)
+    # algorithmic bytes: the input region the trials reference (each channel
+    # up to its own largest delay), read once; the output written once; the
+    # delay table read once
+    alg_bytes = (int(b.nchans * w.nsamp + shift.max(axis=1).astype(np.int64).sum()) * esize
+                 + w.ndm * w.nsamp * 4 + b.nchans * w.ndm * 4)
 
     if args.copy_calibration:
         # a plain copy of known size, so that profiler byte counters can be scaled
@@ -701,6 +783,21 @@ def main() -> int:
         "rtf": rtf, "pct_realtime": 100.0 / rtf, "parity_spot_check": ok,
         "roofline": roofline(w, adds, alg_bytes, kernel_ms, plan.variant),
     }
+    if w.dtype == "f16":
+        # per-trial error against the binary64 oracle on the original float32
+        # data (the float16 quantisation included), on every 16th trial
+        from paper_1111_6399_amd import workloads as wl2
+        x32 = wl2.generate(wl2.lofar("f32", nsamp=w.nsamp, ndm=w.ndm), shift, plan.max_shift)
+        rows = np.arange(0, w.ndm, 16, dtype=np.int32)
+        got = out[torch.from_numpy(rows).long().to(dev)].cpu().numpy().astype(np.float64)
+        want = oracle.dedisperse(x32, shift, w.nsamp, rows=rows)
+        err = np.abs(got - want).max(axis=1) / np.maximum(np.abs(want).max(axis=1), 1e-30)
+        res["f16_error_per_trial"] = {"min": float(err.min()), "median": float(np.median(err)),
+                                      "max": float(err.max()), "trials": int(rows.size),
+                                      "measure": "max_t |y - y64| / max_t |y64|, y64 on the float32 data"}
+        log("float16 per-trial error vs float32 data: min %.3g median %.3g max %.3g"
+            % (err.min(), np.median(err), err.max()))
+        del x32
     if not args.no_cpu_baseline:
         log("timing the oracle on the host ...")
         res["cpu_baseline"] = cpu_baseline(x, shift, w.nsamp, w.ndm, b.nchans)
@@ -708,6 +805,16 @@ def main() -> int:
         log("timing the vectorised host search ...")
         res["cpu_vectorised"] = cpu_vectorised(plan, x, w.nsamp, w.ndm, b.nchans)
         log("host search: %.3g %s (%s)" % (res["cpu_vectorised"]["value"], UNIT, res["cpu_vectorised"]["isa"]))
+    if w.name == "lofar-f32" and not args.no_served:
+        # a short served leg: the MeerKAT-shaped stream at 1.5x real time,
+        # server against the plain FIFO on the same arrivals
+        del xin, out
+        torch.cuda.empty_cache()
+        log("served leg ...")
+        served, plain, splan = served_compare(64, 1.5, 5.0, args.served_duration)
+        res["served"] = {"workload": "served-meerkat: 64 beams, 4096 ch x 4096 trials, blocks of 32768 uint8",
+                         "rate_x_realtime": 1.5, "p99_target_s": P99_TARGET_S, "variant": splan.variant,
+                         "server": served, "plain_fifo": plain}
     print(json.dumps(res), flush=True)
     return 0 if ok else 1
 

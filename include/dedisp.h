@@ -124,9 +124,9 @@ int dedisp_dm_grid(double dm_max, int ndm, double *dm_out);
  * Device memory one dedisp_execute of a plan touches for nsamp >= 0 output
  * samples: in_bytes = nchans*(nsamp + max_shift) samples of the input type;
  * out_bytes = ndm*nsamp*4; staged_bytes = the widened copy a tiled launch of
- * 8-bit or half input works from (16-bit or float samples, padded with zeros
- * to a multiple of 8 samples, allocated stream-ordered by the launch), 0 for
- * float input.  Any output pointer may be NULL.
+ * 8-bit input works from (16-bit samples, padded with zeros to a multiple of
+ * 8 samples, allocated stream-ordered by the launch), 0 for half and float
+ * input (read as they are).  Any output pointer may be NULL.
  */
 int dedisp_plan_footprint(dedisp_plan plan, int64_t nsamp, uint64_t *in_bytes, uint64_t *out_bytes,
                           uint64_t *staged_bytes);
@@ -341,11 +341,13 @@ int dedisp_batch_destroy(dedisp_batch batch);
 int dedisp_server_create(size_t hbm_budget_bytes, int max_inflight, dedisp_server *out_server);
 
 /* Register a beam: plan (not owned; must outlive the server) and block length
- * B >= 1.  Allocates the beam's device buffers against the budget: two windows
- * of nchans x (max_shift + B) samples in the form the kernels read (8-bit
- * samples as 16-bit, half as float) and one raw block of nchans x B samples.
- * DEDISP_ERR_AGAIN if they do not fit.  A request is charged its ndm x B
- * outputs while it runs. */
+ * B >= 1.  Allocates the beam's device buffers against the budget: one ring of
+ * nchans x R samples in the form the kernels read (8-bit samples as 16-bit,
+ * half and float as they are; R = max_shift + B + 4608 rounded up to a
+ * multiple of 8), which holds the history and the newest block (each block is
+ * written once; the history is never copied), and one raw block of
+ * nchans x B samples.  DEDISP_ERR_AGAIN if they do not fit.  A request is
+ * charged its ndm x B outputs while it runs. */
 int dedisp_server_add_beam(dedisp_server server, dedisp_plan plan, int64_t block_nsamp, int *beam_id);
 
 /*

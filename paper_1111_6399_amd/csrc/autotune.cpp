@@ -20,7 +20,8 @@ std::map<std::string, std::pair<int, double>> g_cache;
 bool g_file_loaded = false;
 
 // The delay table fixes everything the kernels' speed depends on apart from
-// the output length and the device, so the key hashes the table.
+// the output length, the device and the kernels themselves, so the key
+// hashes the table and the variant registry (shapes and kernel generation).
 std::string tune_key(dedisp_plan p, int64_t nsamp, int device) {
   uint64_t h = 1469598103934665603ull;  // FNV-1a over the table
   const unsigned char* b = reinterpret_cast<const unsigned char*>(p->shift.data());
@@ -29,8 +30,8 @@ std::string tune_key(dedisp_plan p, int64_t nsamp, int device) {
   std::string arch = "unknown";
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) arch = prop.gcnArchName;
   std::ostringstream os;
-  os << arch << ':' << p->nchans << 'x' << p->ndm << 'x' << nsamp << ":t" << p->dtype << ":v"
-     << dedisp::variant_count() << ':' << std::hex << h;
+  os << arch << ':' << p->nchans << 'x' << p->ndm << 'x' << nsamp << ":t" << p->dtype << ":r" << std::hex
+     << dedisp::registry_signature() << ':' << h;
   return os.str();
 }
 

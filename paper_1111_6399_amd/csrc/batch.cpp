@@ -2,8 +2,8 @@
 // from a HIP graph.
 //
 // The beams that run persistently form groups of one tile variant, one
-// staging kind (8-bit beams are staged as 16-bit pairs, float and half beams
-// as float) and one LDS occupancy (a launch sizes its slots for its widest
+// staging kind (8-bit beams are staged as 16-bit pairs, half beams as halves,
+// float beams as float) and one LDS occupancy (a launch sizes its slots for its widest
 // window, so a beam with a wide delay spread would hold every other beam of
 // its kernel to fewer workgroups per CU), one persistent kernel per group,
 // each compiled for its path only.  Work items are (beam, trial tile, time tile); inside a group beams
@@ -18,9 +18,9 @@
 // launches, captured in the same graph: with one variant for the whole batch,
 // those it cannot stage (delay spread too wide); in the split that follows
 // each plan's own variant, the beams whose plan runs the direct kernel.
-// 8-bit and half inputs are widened into buffers the batch owns (one per such
-// beam) by one kernel at the head of the graph, which reads its jobs from a
-// device table refreshed like the argument tables.
+// 8-bit inputs are widened into buffers the batch owns (one per such beam) by
+// one kernel at the head of the graph, which reads its jobs from a device
+// table refreshed like the argument tables.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,7 +37,7 @@ namespace {
 
 struct BatchGroup {
   int variant = -1;
-  bool pairs = false;                   // 8-bit beams (16-bit pair staging); else float staging
+  int kind = 0;                         // staging kind of its beams (dedisp::StageKind)
   std::vector<int> order;               // beams, longest items first
   int off = 0;                          // first argument slot of the group in each pinned half
   double work = 0.0;                    // adds of its beams
@@ -64,7 +64,7 @@ struct dedisp_batch_s {
   // device state
   dedisp::WidenJob* d_jobs = nullptr;
   int njobs = 0;
-  std::vector<void*> ws;                // widened input per beam (8-bit and half beams)
+  std::vector<void*> ws;                // widened input per beam (8-bit beams)
   dedisp::TiledArgs* h_args = nullptr;  // pinned staging, two halves of nbeams slots
   dedisp::WidenJob* h_jobs = nullptr;   // pinned staging, two halves
   int h_half = 0;
@@ -128,21 +128,21 @@ void form_groups(dedisp_batch b, const std::vector<int>& tiled, const std::vecto
   b->groups.clear();
   b->solo.clear();
   b->solo_variant.clear();
-  std::map<std::tuple<int, bool, int>, size_t> index;
+  std::map<std::tuple<int, int, int>, size_t> index;
   for (int i = 0; i < b->nbeams; ++i) {
     if (tiled[i] < 1) {
       b->solo.push_back(i);
       b->solo_variant.push_back(solo_v[i]);
       continue;
     }
-    const auto key = std::make_tuple(tiled[i], b->plans[i]->dtype == DEDISP_U8,
+    const auto key = std::make_tuple(tiled[i], dedisp::stage_kind(b->plans[i]->dtype),
                                      dedisp::tiled_per_cu(b->plans[i], tiled[i]));
     auto it = index.find(key);
     if (it == index.end()) {
       it = index.emplace(key, b->groups.size()).first;
       BatchGroup g;
       g.variant = std::get<0>(key);
-      g.pairs = std::get<1>(key);
+      g.kind = std::get<1>(key);
       b->groups.push_back(g);
     }
     BatchGroup& g = b->groups[it->second];
@@ -294,7 +294,7 @@ int setup_device(dedisp_batch b, int dev, const void* const* ins, void* const* o
   b->ws.assign(b->nbeams, nullptr);
   for (int i = 0; i < b->nbeams; ++i) {
     const int dt = b->plans[i]->dtype;
-    if (dt == DEDISP_F32) continue;
+    if (dt != DEDISP_U8) continue;
     const size_t bytes = static_cast<size_t>(dedisp::widened_samples(total_samples(b, i))) * dedisp::staged_size(dt);
     if ((e = hipMalloc(&b->ws[i], bytes)) != hipSuccess) return DEDISP_HIP_STATUS(e);
   }
@@ -330,7 +330,7 @@ int build_graph(dedisp_batch b, const void* const* ins, void* const* outs) {
     hipDeviceProp_t prop;
     if ((e = hipGetDeviceProperties(&prop, b->device)) != hipSuccess) return DEDISP_HIP_STATUS(e);
     for (BatchGroup& g : b->groups) {
-      const void* fn = dedisp::batch_kernel(g.variant, g.pairs);
+      const void* fn = dedisp::batch_kernel(g.variant, g.kind);
       if (fn == nullptr) return DEDISP_ERR_INTERNAL;
       if (g.lds > 64 * 1024) {
         const int st = dedisp::allow_large_lds(fn);

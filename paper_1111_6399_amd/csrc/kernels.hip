@@ -15,6 +15,14 @@
 //       sample fetched once from HBM/L2 serves every trial of the tile;
 //  (iii) few operations for the shift: delays are read from a precomputed
 //       table with scalar (wave-uniform) loads, no arithmetic per lane.
+//
+// Three staging kinds (how a sample sits in LDS and how it is added):
+//  * float: float32 input as given, 128-bit LDS reads (4 samples a lane);
+//  * halves: float16 input as given (2 bytes a sample), 64-bit reads, each
+//    half added into a float32 accumulator by one mixed-precision FMA with
+//    1.0 (exactly the float32 add of the widened value);
+//  * pairs: 8-bit input widened to 16 bits beforehand, two samples a 32-bit
+//    word, one integer add for two samples.
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -42,37 +50,38 @@ template <>
 struct Elem<__half> {
   static __device__ __forceinline__ float get(const __half* p, int64_t i) { return __half2float(p[i]); }
 };
-template <>
-struct Elem<uint8_t> {
-  static __device__ __forceinline__ float get(const uint8_t* p, int64_t i) { return static_cast<float>(p[i]); }
-};
 
 // ------------------------------------------------------------ direct --
 
 // One lane per output sample.  The reference-simple variant, also the
 // fallback for plans whose delay spread does not fit any tiled variant.
+// Rows may be rings of `ring` samples (0: plain rows) whose window starts
+// `start` samples in; start < ring and t + delay < ring, so one wrap at most.
 template <typename In>
 __global__ __launch_bounds__(256) void dedisp_direct(const In* __restrict__ in, int64_t pitch,
                                                      void* __restrict__ out_v, int64_t nsamp,
                                                      const int32_t* __restrict__ shift, int ndm_pad,
-                                                     int nchans, int64_t tblocks) {
+                                                     int nchans, int64_t tblocks, int64_t start, int64_t ring) {
   const int64_t bid = blockIdx.x;
   const int d = static_cast<int>(bid / tblocks);
   const int64_t t = (bid % tblocks) * 256 + threadIdx.x;
   if (t >= nsamp) return;
   const int32_t* sh = shift + d;
+  auto at = [&](int c) {
+    int64_t i = t + start + sh[static_cast<int64_t>(c) * ndm_pad];
+    if (ring > 0 && i >= ring) i -= ring;
+    return c * pitch + i;
+  };
   if constexpr (std::is_integral<In>::value) {  // 8-bit samples, or 8-bit samples staged as 16-bit
     int32_t acc = 0;
-    for (int c = 0; c < nchans; ++c)
-      acc += static_cast<int32_t>(in[c * pitch + t + sh[static_cast<int64_t>(c) * ndm_pad]]);
+    for (int c = 0; c < nchans; ++c) acc += static_cast<int32_t>(in[at(c)]);
     static_cast<int32_t*>(out_v)[d * nsamp + t] = acc;
   } else {
     float tot = 0.f;
     for (int c0 = 0; c0 < nchans; c0 += kChanBlock) {
       const int c1 = min(nchans, c0 + kChanBlock);
       float part = 0.f;
-      for (int c = c0; c < c1; ++c)
-        part += Elem<In>::get(in, c * pitch + t + sh[static_cast<int64_t>(c) * ndm_pad]);
+      for (int c = c0; c < c1; ++c) part += Elem<In>::get(in, at(c));
       tot += part;
     }
     static_cast<float*>(out_v)[d * nsamp + t] = tot;
@@ -81,67 +90,31 @@ __global__ __launch_bounds__(256) void dedisp_direct(const In* __restrict__ in, 
 
 // ------------------------------------------------------------- tiled --
 
-// Raw (unconverted) staging registers: four consecutive samples.  Kept raw
-// until they are written to LDS so that the load latency overlaps the
-// accumulation of earlier channels.
-template <typename T>
-struct Raw;
-template <>
-struct Raw<float> {
-  float4 v;
-};
-template <>
-struct Raw<__half> {
-  uint2 v;
-};
-template <>
-struct Raw<uint8_t> {
-  uint32_t v;
-};
-
 typedef int v4i __attribute__((ext_vector_type(4)));
-typedef int v2i __attribute__((ext_vector_type(2)));
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
-// Staging loads go through a buffer resource that covers exactly the part of
-// the channel's window that lies in whole 4-sample groups of the input: lanes
-// past the window read zeros from the range check instead of touching memory.
-// Every thread issues the same number of loads per channel whatever the
-// window length, so the compiler can count them and wait for exactly the
-// channel it is about to consume while later channels stay in flight.
-template <typename T>
-__device__ __forceinline__ Raw<T> load_raw(__amdgpu_buffer_rsrc_t rs, int i) {
-  Raw<T> r;
-  if constexpr (sizeof(T) == 4) {
-    const v4i v = __builtin_amdgcn_raw_buffer_load_b128(rs, 16 * i, 0, 0);
-    r.v = make_float4(__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z), __int_as_float(v.w));
-  } else if constexpr (sizeof(T) == 2) {
-    const v2i v = __builtin_amdgcn_raw_buffer_load_b64(rs, 8 * i, 0, 0);
-    r.v = make_uint2(static_cast<uint32_t>(v.x), static_cast<uint32_t>(v.y));
-  } else {
-    r.v = static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b32(rs, 4 * i, 0, 0));
-  }
-  return r;
-}
-
-__device__ __forceinline__ float h2f(uint32_t bits) {
-  return __half2float(__ushort_as_half(static_cast<unsigned short>(bits)));
-}
-
-template <typename T>
-__device__ __forceinline__ float4 to_float(const Raw<T>& r) {
-  if constexpr (sizeof(T) == 4) {
-    return r.v;
-  } else if constexpr (sizeof(T) == 2) {
-    return make_float4(h2f(r.v.x & 0xffffu), h2f(r.v.x >> 16), h2f(r.v.y & 0xffffu), h2f(r.v.y >> 16));
-  } else {
-    return make_float4(static_cast<float>(r.v & 0xffu), static_cast<float>((r.v >> 8) & 0xffu),
-                       static_cast<float>((r.v >> 16) & 0xffu), static_cast<float>(r.v >> 24));
-  }
-}
+// Staging kinds.  ES: bytes per staged sample; ALIGN: window starts are
+// aligned to 16 bytes (ALIGN samples); RB: bytes per lane of one LDS read
+// (every read gives a lane 4 samples; lanes 0-62 own 252 samples a read,
+// lane 63 only supplies its neighbour).
+template <int K>
+struct Kind;
+template <>
+struct Kind<kStageFloat> {
+  static constexpr int ES = 4, ALIGN = 4, RB = 16;
+};
+template <>
+struct Kind<kStageHalves> {
+  static constexpr int ES = 2, ALIGN = 8, RB = 8;
+};
+template <>
+struct Kind<kStagePairs> {
+  static constexpr int ES = 2, ALIGN = 8, RB = 8;
+};
 
 // Barrier that orders LDS traffic only: vector loads issued before it stay in
-// flight (a full __syncthreads() would also wait for every outstanding load,
-// i.e. for the prefetch of the next channels).
+// flight (a full __syncthreads() would also wait for every outstanding load).
 __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
@@ -182,18 +155,19 @@ __device__ __forceinline__ uint32_t lds_addr(const void* p) {
 // ------------------------------------------------ LDS read-accumulate --
 //
 // The accumulation is written in inline assembly so that the compiler neither
-// pairs the 64-bit reads into two-address reads (half the bytes per cycle on
-// this chip) nor merges the parity paths of a trial into one block joined by
-// register copies.  Reads run one trial ahead of the adds; a wait on the LDS
-// counter then covers exactly the trial about to be consumed (LDS operations
-// complete in order, so extra outstanding ones only make the wait stricter).
+// pairs the reads into two-address reads nor merges the alignment paths of a
+// trial into one block joined by register copies.  Reads run ahead of the
+// adds; a wait on the LDS counter then covers exactly the trial about to be
+// consumed (LDS operations complete in order, so extra outstanding ones only
+// make the wait stricter).
 
-typedef uint32_t v2u __attribute__((ext_vector_type(2)));
-
-// Lane l reads the 64-bit word at addr + 504*k (addr already holds 8*l).  One
-// read of the wave spans 512 consecutive bytes, conflict free: lanes 0-62 own
-// the first 504 bytes, lane 63 reads the first 8 bytes of the next 504-byte
-// block (the neighbour that lane 62 needs for an odd-aligned trial).
+// Lane l reads its RB bytes at addr + 63*RB*k (addr already holds RB*l).
+// One read of the wave spans 64*RB consecutive bytes, conflict free.
+template <int N>
+__device__ __forceinline__ void lds_reads(uint32_t addr, v4u (&v)[N]) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) asm volatile("ds_read_b128 %0, %1 offset:%2" : "=v"(v[k]) : "v"(addr), "i"(1008 * k));
+}
 template <int N>
 __device__ __forceinline__ void lds_reads(uint32_t addr, v2u (&v)[N]) {
 #pragma unroll
@@ -205,14 +179,20 @@ __device__ __forceinline__ void lds_wait() {
   asm volatile("s_waitcnt lgkmcnt(%0)" ::"i"(N));
 }
 
-// One trial's adds for one channel, both alignments in one assembly block
-// with a scalar branch inside (written as one block so that the two paths
-// share their accumulator registers instead of being joined by copies).
+// One trial's adds for one channel, every alignment in one assembly block
+// with a scalar branch inside (written as one block so that the paths share
+// their accumulator registers instead of being joined by copies).  The
+// position p of the trial's first sample in the slot, in bytes, selects the
+// path: r = its sample index mod 4 inside the aligned read.
 //
-// Float: x[2k], x[2k+1] are the lane's two samples of read k.  Even window
-// position: += lo and hi word of read k.  Odd position: += hi word of read k
-// and lo word of the next lane's read k (DPP wave rotation folded into the
-// add; the halo lane 63 supplies lane 62).
+// Float (4 samples x0..x3 a lane and read): output i of the lane takes x[i+r]
+// from its own read for i + r < 4, else x[i+r-4] of the next lane's read (DPP
+// wave rotation folded into the add; the halo lane 63 supplies lane 62).
+//
+// Halves (words x = (h0, h1), y = (h2, h3)): the same selection, the next
+// lane's words rotated into temporaries first; each half is added by
+// v_fma_mix_f32 acc = h * 1.0 + acc (the product is exact, so this is the
+// float32 add of the widened half).
 //
 // 8-bit pairs: e[] holds sums of samples (2i, 2i+1) of the lane, o[] the same
 // one sample earlier.  Position mod 4 selects the set (bit 0) and whether the
@@ -221,18 +201,26 @@ __device__ __forceinline__ void lds_wait() {
 #define DD_FD(a, x) "v_add_f32_dpp %" #a ", %" #x ", %" #a " wave_rol:1 row_mask:0xf bank_mask:0xf\n\t"
 #define DD_UA(a, x) "v_add_u32 %" #a ", %" #a ", %" #x "\n\t"
 #define DD_UD(a, x) "v_add_u32_dpp %" #a ", %" #x ", %" #a " wave_rol:1 row_mask:0xf bank_mask:0xf\n\t"
+#define DD_MD(t, x) "v_mov_b32_dpp %" #t ", %" #x " wave_rol:1 row_mask:0xf bank_mask:0xf\n\t"
+#define DD_HL(a, x) "v_fma_mix_f32 %" #a ", %" #x ", 1.0, %" #a " op_sel_hi:[1,0,0]\n\t"
+#define DD_HH(a, x) "v_fma_mix_f32 %" #a ", %" #x ", 1.0, %" #a " op_sel:[1,0,0] op_sel_hi:[1,0,0]\n\t"
 
-#define DD_F_EVEN2(a0, a1, x0, x1) DD_FA(a0, x0) DD_FA(a1, x1)
-#define DD_F_ODD2(a0, a1, x0, x1) DD_FA(a0, x1) DD_FD(a1, x0)
+// float, 4 accumulators a0..a3 from x0..x3 at alignment r
+#define DD_F4_0(a0, a1, a2, a3, x0, x1, x2, x3) DD_FA(a0, x0) DD_FA(a1, x1) DD_FA(a2, x2) DD_FA(a3, x3)
+#define DD_F4_1(a0, a1, a2, a3, x0, x1, x2, x3) DD_FA(a0, x1) DD_FA(a1, x2) DD_FA(a2, x3) DD_FD(a3, x0)
+#define DD_F4_2(a0, a1, a2, a3, x0, x1, x2, x3) DD_FA(a0, x2) DD_FA(a1, x3) DD_FD(a2, x0) DD_FD(a3, x1)
+#define DD_F4_3(a0, a1, a2, a3, x0, x1, x2, x3) DD_FA(a0, x3) DD_FD(a1, x0) DD_FD(a2, x1) DD_FD(a3, x2)
+
+// halves, 4 accumulators from words x = (h0, h1), y = (h2, h3), temporaries t, u
+#define DD_H4_0(a0, a1, a2, a3, x, y, t, u) DD_HL(a0, x) DD_HH(a1, x) DD_HL(a2, y) DD_HH(a3, y)
+#define DD_H4_1(a0, a1, a2, a3, x, y, t, u) DD_MD(t, x) DD_HH(a0, x) DD_HL(a1, y) DD_HH(a2, y) DD_HL(a3, t)
+#define DD_H4_2(a0, a1, a2, a3, x, y, t, u) DD_MD(t, x) DD_HL(a0, y) DD_HH(a1, y) DD_HL(a2, t) DD_HH(a3, t)
+#define DD_H4_3(a0, a1, a2, a3, x, y, t, u) DD_MD(t, x) DD_MD(u, y) DD_HH(a0, y) DD_HL(a1, t) DD_HH(a2, t) DD_HL(a3, u)
+
 #define DD_U_AL2(a0, a1, x0, x1) DD_UA(a0, x0) DD_UA(a1, x1)
 #define DD_U_SH2(a0, a1, x0, x1) DD_UA(a0, x1) DD_UD(a1, x0)
 
-#define DD_BR2(P, B, EVEN, ODD)                        \
-  "s_bitcmp1_b32 %" #P ", " #B "\n\t"                 \
-  "s_cbranch_scc1 .Ldd_odd%=\n\t" EVEN "s_branch .Ldd_end%=\n" \
-  ".Ldd_odd%=:\n\t"                                    \
-  "s_nop 1\n\t" ODD ".Ldd_end%=:"
-
+// Four-way scalar branch on bits B0 (low) and B1 of SGPR operand P.
 #define DD_BR4(P, B0, B1, A0, A2, A1, A3)                                              \
   "s_bitcmp1_b32 %" #P ", " #B0 "\n\t"                                               \
   "s_cbranch_scc1 .Ldd_o%=\n\t"                                                       \
@@ -242,43 +230,43 @@ __device__ __forceinline__ void lds_wait() {
   "s_nop 1\n\t" A2 "s_branch .Ldd_end%=\n"                                             \
   ".Ldd_o%=:\n\t"                                                                      \
   "s_bitcmp1_b32 %" #P ", " #B1 "\n\t"                                               \
-  "s_cbranch_scc1 .Ldd_3%=\n\t" A1 "s_branch .Ldd_end%=\n"                            \
+  "s_cbranch_scc1 .Ldd_3%=\n\t"                                                       \
+  "s_nop 1\n\t" A1 "s_branch .Ldd_end%=\n"                                             \
   ".Ldd_3%=:\n\t"                                                                      \
   "s_nop 1\n\t" A3 ".Ldd_end%=:"
+
+#define DD_F4ALL(M)                                                                                   \
+  M(0, 1, 2, 3, 16, 17, 18, 19) M(4, 5, 6, 7, 20, 21, 22, 23) M(8, 9, 10, 11, 24, 25, 26, 27) \
+      M(12, 13, 14, 15, 28, 29, 30, 31)
+#define DD_F2ALL(M) M(0, 1, 2, 3, 8, 9, 10, 11) M(4, 5, 6, 7, 12, 13, 14, 15)
+#define DD_H4ALL(M)                                                                                           \
+  M(0, 1, 2, 3, 18, 19, 16, 17) M(4, 5, 6, 7, 20, 21, 16, 17) M(8, 9, 10, 11, 22, 23, 16, 17) \
+      M(12, 13, 14, 15, 24, 25, 16, 17)
+#define DD_H2ALL(M) M(0, 1, 2, 3, 10, 11, 8, 9) M(4, 5, 6, 7, 12, 13, 8, 9)
 
 template <int N>
 struct TrialAdds;
 
 template <>
-struct TrialAdds<8> {
-  static __device__ __forceinline__ void f32(float* x, const v2u (&v)[8], int p) {
-    asm volatile(DD_BR2(32, 2,
-                        DD_F_EVEN2(0, 1, 16, 17) DD_F_EVEN2(2, 3, 18, 19) DD_F_EVEN2(4, 5, 20, 21)
-                            DD_F_EVEN2(6, 7, 22, 23) DD_F_EVEN2(8, 9, 24, 25) DD_F_EVEN2(10, 11, 26, 27)
-                                DD_F_EVEN2(12, 13, 28, 29) DD_F_EVEN2(14, 15, 30, 31),
-                        DD_F_ODD2(0, 1, 16, 17) DD_F_ODD2(2, 3, 18, 19) DD_F_ODD2(4, 5, 20, 21)
-                            DD_F_ODD2(6, 7, 22, 23) DD_F_ODD2(8, 9, 24, 25) DD_F_ODD2(10, 11, 26, 27)
-                                DD_F_ODD2(12, 13, 28, 29) DD_F_ODD2(14, 15, 30, 31))
+struct TrialAdds<4> {
+  // a[0..15] += the block of 4 128-bit reads
+  static __device__ __forceinline__ void f32(float* x, const v4u (&v)[4], int p) {
+    asm volatile(DD_BR4(32, 2, 3, DD_F4ALL(DD_F4_0), DD_F4ALL(DD_F4_2), DD_F4ALL(DD_F4_1), DD_F4ALL(DD_F4_3))
                  : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]),
                    "+v"(x[7]), "+v"(x[8]), "+v"(x[9]), "+v"(x[10]), "+v"(x[11]), "+v"(x[12]), "+v"(x[13]),
                    "+v"(x[14]), "+v"(x[15])
-                 : "v"(v[0].x), "v"(v[0].y), "v"(v[1].x), "v"(v[1].y), "v"(v[2].x), "v"(v[2].y), "v"(v[3].x),
-                   "v"(v[3].y), "v"(v[4].x), "v"(v[4].y), "v"(v[5].x), "v"(v[5].y), "v"(v[6].x), "v"(v[6].y),
-                   "v"(v[7].x), "v"(v[7].y), "s"(p)
+                 : "v"(v[0].x), "v"(v[0].y), "v"(v[0].z), "v"(v[0].w), "v"(v[1].x), "v"(v[1].y), "v"(v[1].z),
+                   "v"(v[1].w), "v"(v[2].x), "v"(v[2].y), "v"(v[2].z), "v"(v[2].w), "v"(v[3].x), "v"(v[3].y),
+                   "v"(v[3].z), "v"(v[3].w), "s"(p)
                  : "scc");
   }
-};
-
-template <>
-struct TrialAdds<4> {
-  static __device__ __forceinline__ void f32(float* x, const v2u (&v)[4], int p) {
-    asm volatile(DD_BR2(16, 2,
-                        DD_F_EVEN2(0, 1, 8, 9) DD_F_EVEN2(2, 3, 10, 11) DD_F_EVEN2(4, 5, 12, 13)
-                            DD_F_EVEN2(6, 7, 14, 15),
-                        DD_F_ODD2(0, 1, 8, 9) DD_F_ODD2(2, 3, 10, 11) DD_F_ODD2(4, 5, 12, 13)
-                            DD_F_ODD2(6, 7, 14, 15))
+  // a[0..15] += the halves of 4 64-bit reads
+  static __device__ __forceinline__ void f16(float* x, const v2u (&v)[4], int p) {
+    uint32_t t, u;
+    asm volatile(DD_BR4(26, 1, 2, DD_H4ALL(DD_H4_0), DD_H4ALL(DD_H4_2), DD_H4ALL(DD_H4_1), DD_H4ALL(DD_H4_3))
                  : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]),
-                   "+v"(x[7])
+                   "+v"(x[7]), "+v"(x[8]), "+v"(x[9]), "+v"(x[10]), "+v"(x[11]), "+v"(x[12]), "+v"(x[13]),
+                   "+v"(x[14]), "+v"(x[15]), "=&v"(t), "=&v"(u)
                  : "v"(v[0].x), "v"(v[0].y), "v"(v[1].x), "v"(v[1].y), "v"(v[2].x), "v"(v[2].y), "v"(v[3].x),
                    "v"(v[3].y), "s"(p)
                  : "scc");
@@ -305,10 +293,19 @@ struct TrialAdds<4> {
 
 template <>
 struct TrialAdds<2> {
-  static __device__ __forceinline__ void f32(float* x, const v2u (&v)[2], int p) {
-    asm volatile(DD_BR2(8, 2, DD_F_EVEN2(0, 1, 4, 5) DD_F_EVEN2(2, 3, 6, 7),
-                        DD_F_ODD2(0, 1, 4, 5) DD_F_ODD2(2, 3, 6, 7))
-                 : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3])
+  static __device__ __forceinline__ void f32(float* x, const v4u (&v)[2], int p) {
+    asm volatile(DD_BR4(16, 2, 3, DD_F2ALL(DD_F4_0), DD_F2ALL(DD_F4_2), DD_F2ALL(DD_F4_1), DD_F2ALL(DD_F4_3))
+                 : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]),
+                   "+v"(x[7])
+                 : "v"(v[0].x), "v"(v[0].y), "v"(v[0].z), "v"(v[0].w), "v"(v[1].x), "v"(v[1].y), "v"(v[1].z),
+                   "v"(v[1].w), "s"(p)
+                 : "scc");
+  }
+  static __device__ __forceinline__ void f16(float* x, const v2u (&v)[2], int p) {
+    uint32_t t, u;
+    asm volatile(DD_BR4(14, 1, 2, DD_H2ALL(DD_H4_0), DD_H2ALL(DD_H4_2), DD_H2ALL(DD_H4_1), DD_H2ALL(DD_H4_3))
+                 : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]),
+                   "+v"(x[7]), "=&v"(t), "=&v"(u)
                  : "v"(v[0].x), "v"(v[0].y), "v"(v[1].x), "v"(v[1].y), "s"(p)
                  : "scc");
   }
@@ -387,12 +384,24 @@ __device__ __forceinline__ void lds_dma_runs(uint32_t lds, uint32_t voff, const 
                  : "memory", "m0");
 }
 
+__device__ __forceinline__ void lds_dma_k(int k, uint32_t lds, uint32_t voff, const v4i& rs) {
+  if (k >= 4)
+    lds_dma_runs<4>(lds, voff, rs);
+  else if (k == 3)
+    lds_dma_runs<3>(lds, voff, rs);
+  else if (k == 2)
+    lds_dma_runs<2>(lds, voff, rs);
+  else
+    lds_dma_runs<1>(lds, voff, rs);
+}
+
 // LDS read address of a (channel, trial) block: the lane's base plus the
 // trial's byte position in the slot with its alignment bits cleared (two
 // vector operations, so that no scalar instruction is spent on it).
+template <int RB>
 __device__ __forceinline__ uint32_t block_addr(uint32_t vbase, int q) {
   uint32_t r;
-  asm volatile("v_and_b32_e64 %0, %1, -8\n\tv_add_u32 %0, %0, %2" : "=&v"(r) : "s"(q), "v"(vbase));
+  asm volatile("v_and_b32_e64 %0, %1, %3\n\tv_add_u32 %0, %0, %2" : "=&v"(r) : "s"(q), "v"(vbase), "i"(-RB));
   return r;
 }
 
@@ -403,11 +412,8 @@ __device__ __forceinline__ void lds_barrier_asm() {
 }
 
 // Tile kernel body.  The input is staged by loads that write LDS directly
-// (no registers).  Float input (and half input widened to float beforehand)
-// is staged as float32, 4 bytes per sample; 8-bit input, widened beforehand
-// to 16 bits, is staged as pairs of samples in the two 16-bit halves of a
-// word, so that one 32-bit add accumulates two samples exactly (a half holds
-// 256 channels of 255 before it could carry).
+// (no registers), in one of three kinds (float, halves, 16-bit pairs of 8-bit
+// samples widened beforehand).
 //
 // Channels are processed in stages of CG, two stages alternating in LDS (one
 // slot per channel).  Channel c0 + g of every stage is loaded by the first
@@ -420,30 +426,35 @@ __device__ __forceinline__ void lds_barrier_asm() {
 // The loads of a channel go through a buffer descriptor based at its row
 // (rounded down to 16 bytes) that reaches to the end of the input, so offsets
 // stay 32-bit however large the input is, and loads past its end return
-// zeros.  Two tables built on the host give, per (trial
-// tile, channel), the byte offset of the window and its number of loads and,
-// per trial, the byte position of its first sample inside the slot, whose low
-// bits carry the alignment the adds need.
-// Both are padded past the last channel, so reading them a stage ahead needs
-// no check; the slots of channels past the last one are zeroed instead of
-// loaded, so adding them needs no check either.
+// zeros.  Rows may also be rings (a streaming beam's history and newest block
+// in one buffer row of ring_bytes): a window then starts start_bytes further
+// on, modulo the ring, and loads that cross the end of the ring continue at
+// its start.  Two tables built on the host give, per (trial tile, channel),
+// the byte offset of the window and its number of loads and, per trial, the
+// byte position of its first sample inside the slot, whose low bits carry the
+// alignment the adds need.  Both are padded past the last channel, so reading
+// them a stage ahead needs no check; the slots of channels past the last one
+// are zeroed instead of loaded, so adding them needs no check either.
 //
-// A (channel, trial) block reads its samples with aligned 64-bit reads,
-// several blocks of reads in flight.  Lanes 0-62 own the output samples; lane
-// 63 only supplies its neighbour when the block's window position is not a
-// multiple of the word pair.  8-bit blocks have a second alignment, the
-// sample within a word: odd positions accumulate into a second set of words
-// that holds every sum one sample earlier, and the two sets are combined into
-// 32-bit totals every 256 channels.  Float sums: channels ascending, summed in
-// blocks of kChanBlock into a partial that is then added to the total (the
-// same order in every variant).
-template <bool kPairs, int DW, int KS, int WD, int WT, int CG, int IW>
+// A (channel, trial) block reads its samples with aligned reads, several
+// blocks of reads in flight.  Lanes 0-62 own the output samples; lane 63 only
+// supplies its neighbour when the block's window position is not a multiple
+// of the read.  8-bit blocks have a second alignment, the sample within a
+// word: odd positions accumulate into a second set of words that holds every
+// sum one sample earlier, and the two sets are combined into 32-bit totals
+// every 256 channels.  Float sums (float and half input): channels ascending,
+// summed in blocks of kChanBlock into a partial that is then added to the
+// total (the same order in every variant).
+template <int KIND, int DW, int KS, int WD, int WT, int CG, int IW>
 __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_tile) {
+  typedef Kind<KIND> K;
+  constexpr bool kPairs = KIND == kStagePairs;
   constexpr int NW = WD * WT;
-  constexpr int SPW = 126 * KS;
+  constexpr int SPW = 126 * KS;  // samples per wave
   constexpr int T = SPW * WT;
-  constexpr int NR = kPairs ? KS / 2 : KS;  // 64-bit LDS reads per lane and block
-  constexpr int ES = kPairs ? 2 : 4;        // bytes per staged sample
+  constexpr int NR = KS / 2;                // LDS reads per lane and block (4 samples each)
+  constexpr int ES = K::ES;                 // bytes per staged sample
+  constexpr int RB = K::RB;                 // bytes per lane and read
   constexpr int WPG = NW / CG;              // waves per issuing group
   constexpr int NB = CG * DW;               // (channel, trial) blocks per stage
   constexpr int QS = DW * WD;               // trials per tile (slot-position row length)
@@ -452,7 +463,8 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
   static_assert(KS % 2 == 0 && (D - 1) * NR <= 15, "tile shape");
   static_assert(NW % CG == 0 && FLUSH % CG == 0, "stage shape");
   static_assert(IW >= 1 && IW <= WPG, "waves that load a window");
-  static_assert((SPW * ES) % 8 == 0, "time offset of a wave keeps the read alignment");
+  static_assert((SPW * ES) % 16 == 0, "time offset of a wave keeps the read alignment");
+  typedef typename std::conditional<RB == 16, v4u, v2u>::type Rd;
   extern __shared__ float4 lds4[];
 
   const int tid = threadIdx.x;
@@ -468,27 +480,37 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
   const int nstages = (nchans + CG - 1) / CG;
   const uint32_t slot_bytes = 1024u * static_cast<uint32_t>(a.runs);
   const uint32_t lds0 = lds_addr(lds4);
-  constexpr int ALIGN = kPairs ? 8 : 4;     // window starts are aligned to 16 bytes
+  constexpr int ALIGN = K::ALIGN;  // window starts are aligned to 16 bytes
   const uint32_t lane16 = 16u * static_cast<uint32_t>(lane);
-  // read base of the lane: its 8 bytes, and the wave's offset along time
-  const uint32_t vlane = lds0 + 8u * static_cast<uint32_t>(lane) + static_cast<uint32_t>(ES * SPW * wt);
-  const uint32_t t0b = static_cast<uint32_t>(ES * t0);
+  // read base of the lane: its RB bytes, and the wave's offset along time
+  const uint32_t vlane = lds0 + RB * static_cast<uint32_t>(lane) + static_cast<uint32_t>(ES * SPW * wt);
+  const uint32_t t0b = static_cast<uint32_t>(ES * t0) + a.start_bytes;
+  const uint32_t ring = a.ring_bytes;  // 0: plain rows
   cint32* wb = (cint32*)(a.wbase) + 2 * (static_cast<int64_t>(dm_tile) * (nchans + kGeoPad) + grp);
   cint32* sp = (cint32*)(a.spos) + static_cast<int64_t>(dm_tile) * (nchans + kGeoPad) * QS + wd * DW;
 
-  // The last 1-3 samples of a float input (past the last whole group of 4)
-  // are read once here; the slot holding them patches them in.  (Widened
-  // inputs are padded to whole groups.)
-  float tail[3] = {0.f, 0.f, 0.f};
+  // The samples of a float or half input past its last whole 16 bytes
+  // (1-3 floats, 1-7 halves) are read once here; the slot holding them
+  // patches them in.  (Widened inputs and rings are whole.)
+  uint32_t tailw[4] = {0u, 0u, 0u, 0u};
   int c_tail = nchans;  // first channel whose window can reach them
-  const bool has_tail = !kPairs && a.ntail > 0;  // the same for the whole launch
+  const bool has_tail = !kPairs && ring == 0 && a.ntail > 0;  // the same for the whole launch
   if (has_tail) {
-    const float* inf = static_cast<const float*>(a.in);
+    if constexpr (KIND == kStageFloat) {
+      const uint32_t* in32 = static_cast<const uint32_t*>(a.in);
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-      if (k < a.ntail) tail[k] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(inf[a.total4 + k])));
+      for (int k = 0; k < 3; ++k)
+        if (k < a.ntail) tailw[k] = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(in32[a.total16 + k])));
+    } else {
+      const uint16_t* in16 = static_cast<const uint16_t*>(a.in);
+#pragma unroll
+      for (int k = 0; k < 7; ++k)
+        if (k < a.ntail)
+          tailw[k >> 1] |= static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(in16[a.total16 + k])))
+                           << (16 * (k & 1));
+    }
     // a window ends before c*pitch + t0 + max_shift + T + 10
-    const int64_t lim = a.total4 - t0 - a.max_shift - (T + 10);
+    const int64_t lim = a.total16 - t0 - a.max_shift - (T + 10);
     c_tail = lim < 0 ? 0 : static_cast<int>(lim / a.pitch) + 1;
   }
 
@@ -504,19 +526,30 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
     if (c < nchans) {
       if (gq >= IW || 4 * gq >= runs) return;
       const int64_t rb = row_base(c);
-      const v4i rs = buffer_words(static_cast<const char*>(a.in) + rb, a.total4 * ES - rb);
+      const v4i rs = buffer_words(static_cast<const char*>(a.in) + rb, ring ? static_cast<int64_t>(ring)
+                                                                             : a.total16 * ES - rb);
       uint32_t lds = __builtin_amdgcn_readfirstlane(lds0 + slot + 4096u * gq);
-      uint32_t voff = wbase + t0b + lane16 + 4096u * gq;
-      for (int i = 4 * gq; i < runs; i += 4 * IW, lds += 4096u * IW, voff += 4096u * IW) {
+      uint32_t u = wbase + t0b + 4096u * gq;  // wave-uniform byte offset of the chunk in the row
+      for (int i = 4 * gq; i < runs; i += 4 * IW, lds += 4096u * IW, u += 4096u * IW) {
         const int k = runs - i;
-        if (k >= 4)
-          lds_dma_runs<4>(lds, voff, rs);
-        else if (k == 3)
-          lds_dma_runs<3>(lds, voff, rs);
-        else if (k == 2)
-          lds_dma_runs<2>(lds, voff, rs);
-        else
-          lds_dma_runs<1>(lds, voff, rs);
+        if (ring == 0) {
+          lds_dma_k(k, lds, u + lane16, rs);
+        } else {
+          // offsets stay below twice the ring (rings are longer than any
+          // window plus a tile), so one subtraction wraps them
+          uint32_t w = u >= ring ? u - ring : u;
+          if (w + 1024u * static_cast<uint32_t>(k < 4 ? k : 4) <= ring) {
+            lds_dma_k(k, lds, w + lane16, rs);
+          } else {  // the chunk crosses the end of the ring: run by run, lane by lane
+            for (int m = 0; m < 4 && m < k; ++m) {
+              uint32_t wm = w + 1024u * m;
+              if (wm >= ring) wm -= ring;
+              uint32_t vo = wm + lane16;
+              if (vo >= ring) vo -= ring;
+              lds_dma_runs<1>(lds + 1024u * m, vo, rs);
+            }
+          }
+        }
       }
     } else if (c < nstages * CG && gq == 0) {
       for (int m = 0; m < a.runs; ++m)
@@ -524,28 +557,28 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
             make_float4(0.f, 0.f, 0.f, 0.f);
     }
   };
-  // After the loads of channel c landed: the partial last group of a float
-  // input, if the slot holds it, is patched in by the lane that loaded its
-  // place.
+  // After the loads of channel c landed: the partial last 16 bytes of the
+  // input, if the slot holds them, are patched in by the lane that loaded
+  // their place.
   auto patch = [&](int c, uint32_t wbase, int runs, uint32_t slot) {
     if (kPairs || c >= nchans || c < c_tail) return;
-    const int64_t off = static_cast<int64_t>(a.total4) * 4 - (row_base(c) + wbase + t0b);
+    const int64_t off = static_cast<int64_t>(a.total16) * ES - (row_base(c) + wbase + t0b);
     if (off < 0 || off >= 1024 * static_cast<int64_t>(runs)) return;
     if ((off >> 12) % IW != gq) return;  // the wave that loaded its 4 KB
     const uint32_t o = static_cast<uint32_t>(off);
     if (lane == ((o >> 4) & 63))
-      *reinterpret_cast<float4*>(reinterpret_cast<char*>(lds4) + slot + o) =
-          make_float4(tail[0], tail[1], tail[2], 0.f);
+      *reinterpret_cast<uint4*>(reinterpret_cast<char*>(lds4) + slot + o) =
+          make_uint4(tailw[0], tailw[1], tailw[2], tailw[3]);
   };
 
   // Accumulators.  Float: acc0 = partial of the current block of channels,
   // tot = total.  8-bit: acc0/acc1 = words of two 16-bit sums (acc1 one
   // sample earlier), tot = 32-bit totals.
-  constexpr int NA = 2 * NR;
+  constexpr int NA = kPairs ? 2 * NR : 4 * NR;
   typedef typename std::conditional<kPairs, uint32_t, float>::type Acc;
   Acc acc0[DW][NA];
   Acc acc1[DW][kPairs ? NA : 1];
-  Acc tot[DW][kPairs ? 4 * NR : NA];
+  Acc tot[DW][4 * NR];
 #pragma unroll
   for (int j = 0; j < DW; ++j) {
 #pragma unroll
@@ -553,7 +586,7 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
 #pragma unroll
     for (int k = 0; k < (kPairs ? NA : 1); ++k) acc1[j][k] = 0;
 #pragma unroll
-    for (int k = 0; k < (kPairs ? 4 * NR : NA); ++k) tot[j][k] = 0;
+    for (int k = 0; k < 4 * NR; ++k) tot[j][k] = 0;
   }
   auto flush = [&]() {
     if constexpr (kPairs) {
@@ -607,8 +640,8 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
 
     // read address of block b (channel c0 + b / DW, trial b % DW), formed right
     // before its reads so that only the blocks in flight hold one
-    auto ba = [&](int b) { return block_addr(vlane + sbase + (b / DW) * slot_bytes, q[b / DW][b % DW]); };
-    v2u rb[D][NR];
+    auto ba = [&](int b) { return block_addr<RB>(vlane + sbase + (b / DW) * slot_bytes, q[b / DW][b % DW]); };
+    Rd rb[D][NR];
 #pragma unroll
     for (int b = 0; b < D && b < NB; ++b) lds_reads<NR>(ba(b), rb[b]);
     // scalar loads for later stages, consumed a stage from now
@@ -628,8 +661,10 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
         lds_wait<NR>();
       else
         lds_wait<0>();
-      if constexpr (kPairs)
+      if constexpr (KIND == kStagePairs)
         TrialAdds<NR>::u8(acc0[b % DW], acc1[b % DW], rb[b % D], q[b / DW][b % DW]);
+      else if constexpr (KIND == kStageHalves)
+        TrialAdds<NR>::f16(acc0[b % DW], rb[b % D], q[b / DW][b % DW]);
       else
         TrialAdds<NR>::f32(acc0[b % DW], rb[b % D], q[b / DW][b % DW]);
       if (b + D < NB) lds_reads<NR>(ba(b + D), rb[(b + D) % D]);
@@ -653,10 +688,10 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
   for (int j = 0; j < DW; ++j) {
     const int d = dw0 + j;
     if (d >= a.ndm) break;
-    if constexpr (kPairs) {
 #pragma unroll
-      for (int k = 0; k < NR; ++k) {
-        const int64_t t = static_cast<int64_t>(t0) + wt * SPW + 4 * lane + 252 * k;
+    for (int k = 0; k < NR; ++k) {
+      const int64_t t = static_cast<int64_t>(t0) + wt * SPW + 4 * lane + 252 * k;
+      if constexpr (kPairs) {
         int32_t* o = static_cast<int32_t*>(a.out) + d * nsamp + t;
         if (t + 3 < nsamp) {
           const int4 w4 = make_int4(static_cast<int32_t>(tot[j][4 * k]), static_cast<int32_t>(tot[j][4 * k + 1]),
@@ -667,27 +702,32 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
           for (int i = 0; i < 4; ++i)
             if (t + i < nsamp) o[i] = static_cast<int32_t>(tot[j][4 * k + i]);
         }
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < NR; ++k) {
-        const int64_t t = static_cast<int64_t>(t0) + wt * SPW + 2 * lane + 126 * k;
+      } else {
         float* o = static_cast<float*>(a.out) + d * nsamp + t;
-        if (t + 1 < nsamp) {
-          const float2 w2 = make_float2(tot[j][2 * k], tot[j][2 * k + 1]);
-          __builtin_memcpy(o, &w2, 8);
-        } else if (t < nsamp) {
-          *o = tot[j][2 * k];
+        if (t + 3 < nsamp) {
+          const float4 w4 = make_float4(tot[j][4 * k], tot[j][4 * k + 1], tot[j][4 * k + 2], tot[j][4 * k + 3]);
+          __builtin_memcpy(o, &w4, 16);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (t + i < nsamp) o[i] = tot[j][4 * k + i];
         }
       }
     }
   }
 }
 
+// Widening of 8-bit input to 16 bits into a buffer padded with zeros to npad
+// samples (a multiple of 8): 8 samples per thread.
+__device__ __forceinline__ uint4 widen8(uint2 w) {
+  uint4 o;
+  o.x = (w.x & 0xffu) | ((w.x & 0xff00u) << 8);
+  o.y = ((w.x >> 16) & 0xffu) | ((w.x >> 8) & 0xff0000u);
+  o.z = (w.y & 0xffu) | ((w.y & 0xff00u) << 8);
+  o.w = ((w.y >> 16) & 0xffu) | ((w.y >> 8) & 0xff0000u);
+  return o;
+}
 
-// Widening of 8-bit input to 16 bits and of half input to float, into a
-// buffer padded with zeros to npad samples (a multiple of 8): 8 samples per
-// thread.
 __global__ __launch_bounds__(256) void widen_u8(const uint8_t* __restrict__ in, uint16_t* __restrict__ out,
                                                 int64_t n, int64_t npad) {
   const int64_t i = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) * 8;
@@ -695,113 +735,88 @@ __global__ __launch_bounds__(256) void widen_u8(const uint8_t* __restrict__ in, 
   if (i + 8 <= n) {
     uint2 w;
     __builtin_memcpy(&w, in + i, 8);
-    uint4 o;
-    o.x = (w.x & 0xffu) | ((w.x & 0xff00u) << 8);
-    o.y = ((w.x >> 16) & 0xffu) | ((w.x >> 8) & 0xff0000u);
-    o.z = (w.y & 0xffu) | ((w.y & 0xff00u) << 8);
-    o.w = ((w.y >> 16) & 0xffu) | ((w.y >> 8) & 0xff0000u);
-    *reinterpret_cast<uint4*>(out + i) = o;
+    *reinterpret_cast<uint4*>(out + i) = widen8(w);
   } else {
 #pragma unroll
     for (int k = 0; k < 8; ++k) out[i + k] = i + k < n ? in[i + k] : 0;
   }
 }
 
-__global__ __launch_bounds__(256) void widen_f16(const __half* __restrict__ in, float* __restrict__ out, int64_t n,
-                                                 int64_t npad) {
-  const int64_t i = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) * 8;
-  if (i >= npad) return;
-  if (i + 8 <= n) {
-    uint4 w;
-    __builtin_memcpy(&w, in + i, 16);
-    float4 lo = make_float4(h2f(w.x & 0xffffu), h2f(w.x >> 16), h2f(w.y & 0xffffu), h2f(w.y >> 16));
-    float4 hi = make_float4(h2f(w.z & 0xffffu), h2f(w.z >> 16), h2f(w.w & 0xffffu), h2f(w.w >> 16));
-    reinterpret_cast<float4*>(out + i)[0] = lo;
-    reinterpret_cast<float4*>(out + i)[1] = hi;
-  } else {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) out[i + k] = i + k < n ? __half2float(in[i + k]) : 0.f;
-  }
-}
-
-
-// Staged form of a sample: 8-bit samples widen to 16 bits, half to float.
-__device__ __forceinline__ uint16_t stage_of(uint8_t x) { return x; }
-__device__ __forceinline__ float stage_of(__half x) { return __half2float(x); }
-__device__ __forceinline__ float stage_of(float x) { return x; }
-
-// Assembly of one streaming window [nchans][tail + block] in staged form:
-// the first `tail` samples of each channel row are the last `tail` of the
-// previous window (already staged), or zeros, and the rest is the new block
-// ([nchans][block], raw) widened.  Rows are strided over blockIdx.y, the
-// samples of a row over blockIdx.x and the lanes, one sample per lane, so
-// every wave reads and writes contiguous runs.
-template <typename In, typename St>
-__global__ __launch_bounds__(256) void assemble_window(const St* __restrict__ prev, const In* __restrict__ blk,
-                                                       St* __restrict__ dst, int64_t tail, int64_t block,
-                                                       int nchans, int zero_tail) {
-  const int64_t pitch = tail + block;
-  for (int c = blockIdx.y; c < nchans; c += gridDim.y) {
-    St* d = dst + c * pitch;
-    const St* h = prev + c * pitch + block;
-    const In* b = blk + c * block;
-    for (int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; j < pitch;
-         j += static_cast<int64_t>(gridDim.x) * 256) {
-      St v;
-      if (j < tail)
-        v = zero_tail ? St(0) : h[j];
-      else
-        v = stage_of(b[j - tail]);
-      d[j] = v;
+// Widening of the 8-bit inputs of a batch: blockIdx.y selects the job, the
+// blocks of a job stride over its samples, 8 per thread.
+__global__ __launch_bounds__(256) void widen_job_kernel(const WidenJob* __restrict__ jobs) {
+  const WidenJob j = jobs[blockIdx.y];
+  const uint8_t* in = static_cast<const uint8_t*>(j.in);
+  uint16_t* out = static_cast<uint16_t*>(j.ws);
+  for (int64_t i = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) * 8; i < j.npad;
+       i += static_cast<int64_t>(gridDim.x) * 256 * 8) {
+    if (i + 8 <= j.n) {
+      uint2 w;
+      __builtin_memcpy(&w, in + i, 8);
+      *reinterpret_cast<uint4*>(out + i) = widen8(w);
+    } else {
+      for (int k = 0; k < 8; ++k) out[i + k] = i + k < j.n ? in[i + k] : 0;
     }
   }
 }
 
-// One launch of a tile variant: 8-bit input (widened to 16 bits) as pairs,
-// float and half input (widened to float) as float32.
-template <bool kPairs, int DW, int KS, int WD, int WT, int CG, int IW>
+// A streaming block [nchans][block] (raw) appended to its beam's ring rows
+// [nchans][ring] in staged form (8-bit widened to 16 bits; float and half as
+// they are), sample j of a row at ring position (pos + j) mod ring.  Rows are
+// strided over blockIdx.y, 8 samples per thread over blockIdx.x: with pos,
+// block and ring multiples of 8 each thread moves 8 aligned samples (no
+// group crosses the end of the ring), otherwise it moves them one by one.
+template <typename In, typename St>
+__global__ __launch_bounds__(256) void ring_append(const In* __restrict__ blk, St* __restrict__ ring_rows,
+                                                   int64_t block, int64_t ring, int64_t pos, int nchans) {
+  const bool vec = (pos % 8) == 0 && (block % 8) == 0 && (ring % 8) == 0;
+  for (int c = blockIdx.y; c < nchans; c += gridDim.y) {
+    const In* src = blk + c * block;
+    St* dst = ring_rows + c * ring;
+    for (int64_t j = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) * 8; j < block;
+         j += static_cast<int64_t>(gridDim.x) * 256 * 8) {
+      int64_t p = pos + j;
+      if (p >= ring) p -= ring;
+      if (vec) {
+        if constexpr (sizeof(In) == 1) {
+          uint2 w;
+          __builtin_memcpy(&w, src + j, 8);
+          *reinterpret_cast<uint4*>(dst + p) = widen8(w);
+        } else {
+          constexpr int NV = sizeof(In) * 8 / 16;  // 16-byte vectors per 8 samples
+#pragma unroll
+          for (int v = 0; v < NV; ++v)
+            reinterpret_cast<uint4*>(dst + p)[v] = reinterpret_cast<const uint4*>(src + j)[v];
+        }
+      } else {
+        for (int k = 0; k < 8 && j + k < block; ++k) {
+          int64_t pk = p + k;
+          if (pk >= ring) pk -= ring;
+          if constexpr (sizeof(In) == 1)
+            dst[pk] = static_cast<St>(src[j + k]);
+          else
+            dst[pk] = src[j + k];
+        }
+      }
+    }
+  }
+}
+
+// One launch of a tile variant for one staging kind.
+template <int KIND, int DW, int KS, int WD, int WT, int CG, int IW>
 __global__ __launch_bounds__(64 * WD * WT) void dedisp_tiled(const TiledArgs a) {
   int dm_tile, t_tile;
   if (!tile_of(a, dm_tile, t_tile)) return;  // padding block of the last group
-  tile_dma<kPairs, DW, KS, WD, WT, CG, IW>(a, dm_tile, t_tile);
-}
-
-// Widening of the inputs of a batch: blockIdx.y selects the job, the blocks
-// of a job stride over its samples, 8 per thread.
-__global__ __launch_bounds__(256) void widen_job_kernel(const WidenJob* __restrict__ jobs) {
-  const WidenJob j = jobs[blockIdx.y];
-  for (int64_t i = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) * 8; i < j.npad;
-       i += static_cast<int64_t>(gridDim.x) * 256 * 8) {
-    if (j.dtype == DEDISP_U8) {
-      const uint8_t* in = static_cast<const uint8_t*>(j.in);
-      uint16_t* out = static_cast<uint16_t*>(j.ws);
-      if (i + 8 <= j.n) {
-        uint2 w;
-        __builtin_memcpy(&w, in + i, 8);
-        uint4 o;
-        o.x = (w.x & 0xffu) | ((w.x & 0xff00u) << 8);
-        o.y = ((w.x >> 16) & 0xffu) | ((w.x >> 8) & 0xff0000u);
-        o.z = (w.y & 0xffu) | ((w.y & 0xff00u) << 8);
-        o.w = ((w.y >> 16) & 0xffu) | ((w.y >> 8) & 0xff0000u);
-        *reinterpret_cast<uint4*>(out + i) = o;
-      } else {
-        for (int k = 0; k < 8; ++k) out[i + k] = i + k < j.n ? in[i + k] : 0;
-      }
-    } else {
-      const __half* in = static_cast<const __half*>(j.in);
-      float* out = static_cast<float*>(j.ws);
-      for (int k = 0; k < 8; ++k) out[i + k] = i + k < j.n ? __half2float(in[i + k]) : 0.f;
-    }
-  }
+  tile_dma<KIND, DW, KS, WD, WT, CG, IW>(a, dm_tile, t_tile);
 }
 
 // Persistent batch kernel: resident workgroups pull (beam, trial tile, time
 // tile) items from atomic counters (one per XCD) until none are left.  Items are
 // numbered beam by beam, beams in order of decreasing cost per item (longest
 // items first), and inside a beam in the same groups as a single launch.  One
-// kernel per staging kind (its beams are all 8-bit, or all float and half),
-// so that each carries the registers of one path only.
-template <bool kPairs, int DW, int KS, int WD, int WT, int CG, int IW>
+// kernel per staging kind, so that each carries the registers of one path
+// only.
+template <int KIND, int DW, int KS, int WD, int WT, int CG, int IW>
 __global__ __launch_bounds__(64 * WD * WT) void dedisp_batch_persistent(const BatchArgs b) {
   __shared__ long long item_s;
   // Blocks run on XCD blockIdx.x mod 8.  Items go out in chunks of
@@ -834,7 +849,7 @@ __global__ __launch_bounds__(64 * WD * WT) void dedisp_batch_persistent(const Ba
     // wave-uniform: kept in scalar registers (the divisions above run on the vector unit)
     const int dm_tile = __builtin_amdgcn_readfirstlane((g % a.n_dm_groups) * a.gd + i % a.gd);
     const int t_tile = __builtin_amdgcn_readfirstlane((g / a.n_dm_groups) * a.gt + i / a.gd);
-    if (dm_tile < a.n_dm_tiles && t_tile < a.n_t_tiles) tile_dma<kPairs, DW, KS, WD, WT, CG, IW>(a, dm_tile, t_tile);
+    if (dm_tile < a.n_dm_tiles && t_tile < a.n_t_tiles) tile_dma<KIND, DW, KS, WD, WT, CG, IW>(a, dm_tile, t_tile);
     lds_barrier();  // every wave is done with this item's LDS before the next
   }
 }
@@ -847,19 +862,21 @@ __global__ void reset_counter(unsigned long long* c) {
 
 struct Variant {
   TileShape shape;
-  int cg;             // channels per stage
-  const void* fn[3];  // by dtype: U8, F16, F32
-  const void* batch[2];  // persistent batch kernel: float staging, 16-bit pair staging
+  int cg;                // channels per stage
+  int iw;                // waves of a group that load a window
+  const void* fn[3];     // by staging kind: float, halves, pairs
+  const void* batch[3];  // persistent batch kernel by staging kind
 };
 
-#define DEDISP_VARIANT(DW, KS, WD, WT, CG, IW)                                                      \
-  Variant {                                                                                        \
-    TileShape{DW, KS, WD, WT}, CG,                                                                 \
-        {reinterpret_cast<const void*>(&dedisp_tiled<true, DW, KS, WD, WT, CG, IW>),                \
-         reinterpret_cast<const void*>(&dedisp_tiled<false, DW, KS, WD, WT, CG, IW>),               \
-         reinterpret_cast<const void*>(&dedisp_tiled<false, DW, KS, WD, WT, CG, IW>)},              \
-        {reinterpret_cast<const void*>(&dedisp_batch_persistent<false, DW, KS, WD, WT, CG, IW>),      \
-         reinterpret_cast<const void*>(&dedisp_batch_persistent<true, DW, KS, WD, WT, CG, IW>)}       \
+#define DEDISP_VARIANT(DW, KS, WD, WT, CG, IW)                                                             \
+  Variant {                                                                                               \
+    TileShape{DW, KS, WD, WT}, CG, IW,                                                                    \
+        {reinterpret_cast<const void*>(&dedisp_tiled<kStageFloat, DW, KS, WD, WT, CG, IW>),               \
+         reinterpret_cast<const void*>(&dedisp_tiled<kStageHalves, DW, KS, WD, WT, CG, IW>),              \
+         reinterpret_cast<const void*>(&dedisp_tiled<kStagePairs, DW, KS, WD, WT, CG, IW>)},              \
+        {reinterpret_cast<const void*>(&dedisp_batch_persistent<kStageFloat, DW, KS, WD, WT, CG, IW>),    \
+         reinterpret_cast<const void*>(&dedisp_batch_persistent<kStageHalves, DW, KS, WD, WT, CG, IW>),   \
+         reinterpret_cast<const void*>(&dedisp_batch_persistent<kStagePairs, DW, KS, WD, WT, CG, IW>)}    \
   }
 
 // The last argument is the number of waves of a group that share a window's
@@ -881,21 +898,28 @@ const Variant kVariants[] = {
 };
 constexpr int kNumTiled = sizeof(kVariants) / sizeof(kVariants[0]);
 
+// Bumped whenever the tile kernels change in a way that can change which
+// variant is fastest (the autotuner's cache keys carry it).
+constexpr int kKernelGeneration = 2;
+
 constexpr size_t kMaxLds = 160 * 1024;
+
+// Bytes a lane reads past a block's last sample (the halo lane's read) for a
+// staging kind.
+inline int halo_bytes(int dtype) { return staged_size(dtype) == 4 ? 16 : 8; }
 
 // 1 KB loads per LDS slot (one channel's window) a tiled variant needs for
 // this plan, or 0 if the plan's delay spread is too wide for the variant's
 // LDS.  A window covers the tile's samples, the delay spread of its trials,
-// the alignment of its start (to 4 samples for float staging, 8 for 16-bit
-// pairs) and the neighbour word the halo lane reads past the last sample.
-// Two stages of `cg` slots are live.
+// the alignment of its start (16 bytes) and the halo lane's read past the
+// last sample.  Two stages of `cg` slots are live.
 int slot_runs(dedisp_plan p, const Variant& v) {
   const std::vector<int2>& w = host_windows(p, v.shape.dms());
   int spread = 0;
   for (const int2& x : w) spread = std::max(spread, x.y - x.x);
   const int64_t es = staged_size(p->dtype);
-  const int64_t align = p->dtype == DEDISP_U8 ? 8 : 4;
-  const int64_t bytes = es * (static_cast<int64_t>(spread) + align - 1 + v.shape.samples()) + 8;
+  const int64_t align = stage_align(p->dtype);
+  const int64_t bytes = es * (static_cast<int64_t>(spread) + align - 1 + v.shape.samples()) + halo_bytes(p->dtype);
   const int64_t runs = (bytes + 1023) / 1024;
   if (2 * v.cg * runs * 1024 > static_cast<int64_t>(kMaxLds) - 256) return 0;  // 256 B for static LDS
   return static_cast<int>(runs);
@@ -903,8 +927,7 @@ int slot_runs(dedisp_plan p, const Variant& v) {
 
 // The tiled kernels address a row (and a window past its end) with 32-bit
 // byte offsets from the row's start.
-bool offsets_fit(dedisp_plan p, int64_t nsamp) {
-  const int64_t pitch = nsamp + p->max_shift;
+bool offsets_fit(dedisp_plan p, int64_t pitch) {
   return (pitch + 16) * staged_size(p->dtype) + (static_cast<int64_t>(1) << 20) < (static_cast<int64_t>(1) << 32);
 }
 
@@ -913,6 +936,23 @@ bool offsets_fit(dedisp_plan p, int64_t nsamp) {
 int variant_count() { return 1 + kNumTiled; }
 
 TileShape variant_shape(int v) { return kVariants[v - 1].shape; }
+
+uint64_t registry_signature() {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the registry's parameters
+  auto mix = [&h](int x) {
+    for (int k = 0; k < 4; ++k) h = (h ^ static_cast<unsigned char>(x >> (8 * k))) * 1099511628211ull;
+  };
+  mix(kKernelGeneration);
+  for (const Variant& v : kVariants) {
+    mix(v.shape.dw);
+    mix(v.shape.ks);
+    mix(v.shape.wd);
+    mix(v.shape.wt);
+    mix(v.cg);
+    mix(v.iw);
+  }
+  return h;
+}
 
 int tiled_per_cu(dedisp_plan p, int v) {
   if (v < 1 || v > kNumTiled) return 0;
@@ -936,27 +976,29 @@ int default_variant(dedisp_plan p) {
 
 namespace {
 
-// The direct kernel over input of sample type In (raw or staged).
+// The direct kernel over input of sample type In (raw or staged), rows of
+// `pitch` samples (rings of `ring` samples whose windows start `start` in,
+// or plain rows when ring = 0).
 template <typename In>
-int launch_direct(dedisp_plan p, const DeviceTables* dt, const void* in, void* out, int64_t nsamp, hipStream_t s) {
-  const int64_t pitch = nsamp + p->max_shift;
+int launch_direct(dedisp_plan p, const DeviceTables* dt, const void* in, void* out, int64_t nsamp, int64_t pitch,
+                  int64_t start, int64_t ring, hipStream_t s) {
   const int64_t tblocks = (nsamp + 255) / 256;
   const int64_t nblocks = tblocks * p->ndm;
   if (nblocks > INT32_MAX) return DEDISP_ERR_INVALID_ARG;
   hipLaunchKernelGGL(dedisp_direct<In>, dim3(static_cast<unsigned>(nblocks)), dim3(256), 0, s,
-                     static_cast<const In*>(in), pitch, out, nsamp, dt->shift, p->ndm_pad, p->nchans, tblocks);
+                     static_cast<const In*>(in), pitch, out, nsamp, dt->shift, p->ndm_pad, p->nchans, tblocks, start,
+                     ring);
   return DEDISP_HIP_STATUS(hipGetLastError());
 }
 
-// A tiled variant over staged input (float input as given, 8-bit and half
-// input widened).
-int launch_tiled(dedisp_plan p, int v, const void* staged, void* out, int64_t nsamp, hipStream_t s) {
+// A tiled variant over staged input.
+int launch_tiled(dedisp_plan p, int v, const StagedRows& rows, void* out, int64_t nsamp, hipStream_t s) {
   TiledArgs a;
   size_t lds = 0;
   int64_t nblocks = 0;
   int threads = 0;
-  int st = tiled_args(p, v, staged, out, nsamp, &a, &lds, &nblocks, &threads);
-  const void* fn = kVariants[v - 1].fn[p->dtype];
+  int st = tiled_args_rows(p, v, rows, out, nsamp, &a, &lds, &nblocks, &threads);
+  const void* fn = kVariants[v - 1].fn[stage_kind(p->dtype)];
   if (st == DEDISP_OK && lds > 64 * 1024) st = allow_large_lds(fn);
   if (st == DEDISP_OK) {
     void* args[] = {&a};
@@ -992,20 +1034,21 @@ int launch(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, hipSt
   DeviceTables* dt = nullptr;
   int st = device_tables(p, dev, &dt);
   if (st != DEDISP_OK) return st;
-  const int64_t total = (nsamp + p->max_shift) * p->nchans;
+  const int64_t pitch = nsamp + p->max_shift;
+  const int64_t total = pitch * p->nchans;
   // the tiled kernels address each row with 32-bit byte offsets; longer rows
   // take the direct kernel
-  if (v > 0 && !offsets_fit(p, nsamp)) v = 0;
+  if (v > 0 && !offsets_fit(p, pitch)) v = 0;
   if (v == 0) {
     switch (p->dtype) {
-      case DEDISP_U8: return launch_direct<uint8_t>(p, dt, in, out, nsamp, s);
-      case DEDISP_F16: return launch_direct<__half>(p, dt, in, out, nsamp, s);
-      default: return launch_direct<float>(p, dt, in, out, nsamp, s);
+      case DEDISP_U8: return launch_direct<uint8_t>(p, dt, in, out, nsamp, pitch, 0, 0, s);
+      case DEDISP_F16: return launch_direct<__half>(p, dt, in, out, nsamp, pitch, 0, 0, s);
+      default: return launch_direct<float>(p, dt, in, out, nsamp, pitch, 0, 0, s);
     }
   }
-  if (p->dtype == DEDISP_F32) return launch_tiled(p, v, in, out, nsamp, s);
-  // 8-bit and half input are widened into a workspace first: the caller's,
-  // else a stream-ordered one
+  if (p->dtype != DEDISP_U8) return launch_tiled(p, v, StagedRows{in, pitch, total, 0, 0}, out, nsamp, s);
+  // 8-bit input is widened into a workspace first: the caller's, else a
+  // stream-ordered one
   void* ws = ws_given;
   if (ws == nullptr) {
     st = keep_pool_memory(dev);
@@ -1014,7 +1057,7 @@ int launch(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, hipSt
     if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
   }
   st = widen(p->dtype, in, ws, total, s);
-  if (st == DEDISP_OK) st = launch_tiled(p, v, ws, out, nsamp, s);
+  if (st == DEDISP_OK) st = launch_tiled(p, v, StagedRows{ws, pitch, widened_samples(total), 0, 0}, out, nsamp, s);
   if (ws_given == nullptr) {
     const int st2 = DEDISP_HIP_STATUS(hipFreeAsync(ws, s));
     if (st == DEDISP_OK) st = st2;
@@ -1022,48 +1065,47 @@ int launch(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, hipSt
   return st;
 }
 
-int launch_staged(dedisp_plan p, int v, const void* staged, void* out, int64_t nsamp, hipStream_t s) {
+int launch_rows(dedisp_plan p, int v, const StagedRows& rows, void* out, int64_t nsamp, hipStream_t s) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
   DeviceTables* dt = nullptr;
   int st = device_tables(p, dev, &dt);
   if (st != DEDISP_OK) return st;
-  if (v > 0 && !offsets_fit(p, nsamp)) v = 0;
+  if (v > 0 && !offsets_fit(p, rows.pitch)) v = 0;
   if (v == 0) {
     // same channel order and float conversion as on raw input
-    if (p->dtype == DEDISP_U8) return launch_direct<uint16_t>(p, dt, staged, out, nsamp, s);
-    return launch_direct<float>(p, dt, staged, out, nsamp, s);
+    switch (p->dtype) {
+      case DEDISP_U8: return launch_direct<uint16_t>(p, dt, rows.in, out, nsamp, rows.pitch, rows.start, rows.ring, s);
+      case DEDISP_F16: return launch_direct<__half>(p, dt, rows.in, out, nsamp, rows.pitch, rows.start, rows.ring, s);
+      default: return launch_direct<float>(p, dt, rows.in, out, nsamp, rows.pitch, rows.start, rows.ring, s);
+    }
   }
-  return launch_tiled(p, v, staged, out, nsamp, s);
+  return launch_tiled(p, v, rows, out, nsamp, s);
 }
 
 size_t staged_bytes(dedisp_plan p, int64_t nsamp) {
   return static_cast<size_t>(widened_samples((nsamp + p->max_shift) * p->nchans)) * staged_size(p->dtype);
 }
 
-int assemble(int dtype, const void* prev, const void* blk, void* dst, int64_t tail, int64_t block, int nchans,
-             bool zero_tail, hipStream_t s) {
-  if (nchans < 1 || tail < 0 || block < 1) return DEDISP_ERR_INVALID_ARG;
-  const int64_t pitch = tail + block;
-  const unsigned gx = static_cast<unsigned>(std::min<int64_t>((pitch + 255) / 256, 32));
+int ring_append(int dtype, const void* blk, void* ring_rows, int64_t block, int64_t ring, int64_t pos, int nchans,
+                hipStream_t s) {
+  if (nchans < 1 || block < 1 || ring < block || pos < 0 || pos >= ring) return DEDISP_ERR_INVALID_ARG;
+  const unsigned gx = static_cast<unsigned>(std::min<int64_t>((block / 8 + 255) / 256 + 1, 64));
   const unsigned gy = static_cast<unsigned>(std::min(nchans, 65535));
-  const int z = zero_tail ? 1 : 0;
   switch (dtype) {
     case DEDISP_U8:
-      hipLaunchKernelGGL((assemble_window<uint8_t, uint16_t>), dim3(gx, gy), dim3(256), 0, s,
-                         static_cast<const uint16_t*>(prev), static_cast<const uint8_t*>(blk),
-                         static_cast<uint16_t*>(dst), tail, block, nchans, z);
+      hipLaunchKernelGGL((ring_append<uint8_t, uint16_t>), dim3(gx, gy), dim3(256), 0, s,
+                         static_cast<const uint8_t*>(blk), static_cast<uint16_t*>(ring_rows), block, ring, pos, nchans);
       break;
     case DEDISP_F16:
-      hipLaunchKernelGGL((assemble_window<__half, float>), dim3(gx, gy), dim3(256), 0, s,
-                         static_cast<const float*>(prev), static_cast<const __half*>(blk), static_cast<float*>(dst),
-                         tail, block, nchans, z);
+      hipLaunchKernelGGL((ring_append<uint16_t, uint16_t>), dim3(gx, gy), dim3(256), 0, s,
+                         static_cast<const uint16_t*>(blk), static_cast<uint16_t*>(ring_rows), block, ring, pos,
+                         nchans);
       break;
     case DEDISP_F32:
-      hipLaunchKernelGGL((assemble_window<float, float>), dim3(gx, gy), dim3(256), 0, s,
-                         static_cast<const float*>(prev), static_cast<const float*>(blk), static_cast<float*>(dst),
-                         tail, block, nchans, z);
+      hipLaunchKernelGGL((ring_append<float, float>), dim3(gx, gy), dim3(256), 0, s, static_cast<const float*>(blk),
+                         static_cast<float*>(ring_rows), block, ring, pos, nchans);
       break;
     default:
       return DEDISP_ERR_INVALID_ARG;
@@ -1080,22 +1122,17 @@ int widen_jobs(const WidenJob* jobs, int njobs, hipStream_t s) {
 int64_t widened_samples(int64_t total) { return (total + 7) / 8 * 8; }
 
 int widen(int dtype, const void* in, void* ws, int64_t total, hipStream_t s) {
+  if (dtype != DEDISP_U8) return DEDISP_ERR_INVALID_ARG;
   const int64_t npad = widened_samples(total);
   const int64_t blocks = (npad / 8 + 255) / 256;
   if (blocks > INT32_MAX) return DEDISP_ERR_INVALID_ARG;
-  if (dtype == DEDISP_U8)
-    hipLaunchKernelGGL(widen_u8, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
-                       static_cast<const uint8_t*>(in), static_cast<uint16_t*>(ws), total, npad);
-  else if (dtype == DEDISP_F16)
-    hipLaunchKernelGGL(widen_f16, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
-                       static_cast<const __half*>(in), static_cast<float*>(ws), total, npad);
-  else
-    return DEDISP_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(widen_u8, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, static_cast<const uint8_t*>(in),
+                     static_cast<uint16_t*>(ws), total, npad);
   return DEDISP_HIP_STATUS(hipGetLastError());
 }
 
-int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, TiledArgs* ap, size_t* lds_out,
-               int64_t* nblocks_out, int* threads_out) {
+int tiled_args_rows(dedisp_plan p, int v, const StagedRows& rows, void* out, int64_t nsamp, TiledArgs* ap,
+                    size_t* lds_out, int64_t* nblocks_out, int* threads_out) {
   if (v < 1 || v > kNumTiled) return DEDISP_ERR_INVALID_ARG;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -1107,27 +1144,28 @@ int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, T
   const int runs = slot_runs(p, var);
   if (runs == 0) return DEDISP_ERR_INVALID_ARG;
   // the tiled kernels address each row with 32-bit byte offsets
-  if (!offsets_fit(p, nsamp)) return DEDISP_ERR_INVALID_ARG;
-  const int64_t pitch = nsamp + p->max_shift;
-  const int64_t total = pitch * p->nchans;
-  const int align = p->dtype == DEDISP_U8 ? 8 : 4;
+  if (!offsets_fit(p, rows.pitch)) return DEDISP_ERR_INVALID_ARG;
+  const int align = stage_align(p->dtype);
   const int es = static_cast<int>(staged_size(p->dtype));
+  if (rows.ring > 0 && (rows.ring % align != 0 || rows.pitch != rows.ring || rows.start < 0 || rows.start >= rows.ring))
+    return DEDISP_ERR_INVALID_ARG;
+  const int pitch_mod = static_cast<int>(rows.pitch % align);
+  const int start_mod = static_cast<int>(rows.start % align);
   const uint32_t* wbase = nullptr;
-  st = device_window_base(p, dev, var.shape.dms(), var.shape.samples(), align, es, static_cast<int>(pitch % align), &wbase);
+  st = device_window_base(p, dev, var.shape.dms(), var.shape.samples(), align, es, pitch_mod, start_mod,
+                          halo_bytes(p->dtype), &wbase);
   if (st != DEDISP_OK) return st;
   const int32_t* spos = nullptr;
-  st = device_slot_pos(p, dev, var.shape.dms(), align, es, static_cast<int>(pitch % align), &spos);
+  st = device_slot_pos(p, dev, var.shape.dms(), align, es, pitch_mod, start_mod, &spos);
   if (st != DEDISP_OK) return st;
   TiledArgs& a = *ap;
-  a.in = in;
-  a.pitch = pitch;
-  if (p->dtype == DEDISP_F32) {
-    a.total4 = total & ~static_cast<int64_t>(3);
-    a.ntail = static_cast<int>(total - a.total4);
-  } else {  // widened input, padded with zeros to whole groups of 8
-    a.total4 = widened_samples(total);
-    a.ntail = 0;
-  }
+  a.in = rows.in;
+  a.pitch = rows.pitch;
+  // staged samples in whole 16-byte groups, and the samples after them
+  a.total16 = rows.total & ~static_cast<int64_t>(16 / es - 1);
+  a.ntail = static_cast<int>(rows.total - a.total16);
+  a.start_bytes = static_cast<uint32_t>(es * (rows.start - start_mod));
+  a.ring_bytes = static_cast<uint32_t>(es * rows.ring);
   a.max_shift = p->max_shift;
   a.out = out;
   a.nsamp = nsamp;
@@ -1140,12 +1178,12 @@ int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, T
   const int64_t n_t_tiles = (nsamp + var.shape.samples() - 1) / var.shape.samples();
   if (n_t_tiles > INT32_MAX / 64) return DEDISP_ERR_INVALID_ARG;
   a.n_t_tiles = static_cast<int>(n_t_tiles);
-  // groups of up to 16 trial tiles x 1 time tile (16-bit pair staging) or
-  // 8 x 3 (float staging), the fastest of a sweep of group shapes on the
+  // groups of up to 16 trial tiles x 1 time tile (16-bit staging) or 8 x 3
+  // (float staging), the fastest of a sweep of group shapes on the
   // LOFAR-shaped and MeerKAT-shaped workloads
-  const bool pairs = p->dtype == DEDISP_U8;
-  a.gd = std::min(pairs ? 16 : 8, a.n_dm_tiles);
-  a.gt = std::min(pairs ? 1 : 3, a.n_t_tiles);
+  const bool narrow = es == 2;
+  a.gd = std::min(narrow ? 16 : 8, a.n_dm_tiles);
+  a.gt = std::min(narrow ? 1 : 3, a.n_t_tiles);
   a.n_dm_groups = (a.n_dm_tiles + a.gd - 1) / a.gd;
   const int64_t n_groups = static_cast<int64_t>(a.n_dm_groups) * ((a.n_t_tiles + a.gt - 1) / a.gt);
   // a multiple of 8 groups, so that every XCD's run of blocks is whole groups
@@ -1155,6 +1193,14 @@ int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, T
   *nblocks_out = nblocks;
   *threads_out = var.shape.threads();
   return DEDISP_OK;
+}
+
+int tiled_args(dedisp_plan p, int v, const void* staged, void* out, int64_t nsamp, TiledArgs* a, size_t* lds,
+               int64_t* nblocks, int* threads) {
+  const int64_t pitch = nsamp + p->max_shift;
+  const int64_t total = pitch * p->nchans;
+  const int64_t staged_total = p->dtype == DEDISP_U8 ? widened_samples(total) : total;
+  return tiled_args_rows(p, v, StagedRows{staged, pitch, staged_total, 0, 0}, out, nsamp, a, lds, nblocks, threads);
 }
 
 // Lift the default 64 KiB cap on dynamic LDS for a kernel, once per process
@@ -1184,20 +1230,21 @@ int prepare(dedisp_plan p, int v, int64_t nsamp) {
   int st = device_tables(p, dev, &dt);
   if (st != DEDISP_OK || v <= 0) return st;
   const int64_t pitch = nsamp + p->max_shift;
-  const int align = p->dtype == DEDISP_U8 ? 8 : 4;
+  const int align = stage_align(p->dtype);
   const int es = static_cast<int>(staged_size(p->dtype));
   const int dms = variant_shape(v).dms();
   const uint32_t* wbase = nullptr;
-  st = device_window_base(p, dev, dms, variant_shape(v).samples(), align, es, static_cast<int>(pitch % align), &wbase);
+  st = device_window_base(p, dev, dms, variant_shape(v).samples(), align, es, static_cast<int>(pitch % align), 0,
+                          halo_bytes(p->dtype), &wbase);
   if (st != DEDISP_OK) return st;
   const int32_t* spos = nullptr;
-  st = device_slot_pos(p, dev, dms, align, es, static_cast<int>(pitch % align), &spos);
+  st = device_slot_pos(p, dev, dms, align, es, static_cast<int>(pitch % align), 0, &spos);
   if (st != DEDISP_OK) return st;
-  return allow_large_lds(kVariants[v - 1].fn[p->dtype]);
+  return allow_large_lds(kVariants[v - 1].fn[stage_kind(p->dtype)]);
 }
 
-const void* batch_kernel(int v, bool pairs) {
-  return (v >= 1 && v <= kNumTiled) ? kVariants[v - 1].batch[pairs ? 1 : 0] : nullptr;
+const void* batch_kernel(int v, int kind) {
+  return (v >= 1 && v <= kNumTiled && kind >= 0 && kind < 3) ? kVariants[v - 1].batch[kind] : nullptr;
 }
 
 const void* reset_kernel() { return reinterpret_cast<const void*>(&reset_counter); }

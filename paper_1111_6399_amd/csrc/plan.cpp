@@ -115,9 +115,9 @@ extern "C" int dedisp_plan_footprint(dedisp_plan p, int64_t nsamp, uint64_t* in_
   if (in_bytes) *in_bytes = total * dedisp::dtype_size(p->dtype);
   if (out_bytes) *out_bytes = static_cast<uint64_t>(p->ndm) * static_cast<uint64_t>(nsamp) * 4u;
   if (staged_bytes)
-    *staged_bytes = p->dtype == DEDISP_F32 ? 0u
-                                           : static_cast<uint64_t>(dedisp::widened_samples(static_cast<int64_t>(total))) *
-                                                 static_cast<uint64_t>(dedisp::staged_size(p->dtype));
+    *staged_bytes = p->dtype != DEDISP_U8 ? 0u
+                                          : static_cast<uint64_t>(dedisp::widened_samples(static_cast<int64_t>(total))) *
+                                                static_cast<uint64_t>(dedisp::staged_size(p->dtype));
   return DEDISP_OK;
 }
 
@@ -213,19 +213,25 @@ int upload(const std::vector<T>& h, T** out) {
   return DEDISP_OK;
 }
 
-// Alignment of the window start c*pitch + t0 + lo (t0 is a multiple of align).
-inline int window_mis(int c, int64_t pitch, int lo, int align) {
-  return static_cast<int>((static_cast<int64_t>(c) * (pitch % align) + lo) % align);
+// Alignment of row c's start in samples: (c*pitch + start) mod align.
+inline int row_phase(int c, int pitch_mod, int start_mod, int align) {
+  return static_cast<int>((static_cast<int64_t>(c) * pitch_mod + start_mod) % align);
+}
+
+// Alignment of the window start c*pitch + start + t0 + lo (t0 is a multiple
+// of align).
+inline int window_mis(int c, int pitch_mod, int start_mod, int lo, int align) {
+  return (row_phase(c, pitch_mod, start_mod, align) + lo % align) % align;
 }
 
 }  // namespace
 
 int device_window_base(dedisp_plan p, int device, int dms_per_tile, int samples, int align, int es, int pitch_mod,
-                       const uint32_t** out) {
+                       int start_mod, int halo, const uint32_t** out) {
   const std::vector<int2>& hw = host_windows(p, dms_per_tile);
   std::lock_guard<std::mutex> g(p->mu);
   DeviceTables& t = p->dev[device];
-  const auto key = std::make_tuple(dms_per_tile, samples, align, es, static_cast<int64_t>(pitch_mod));
+  const auto key = std::make_tuple(dms_per_tile, samples, align, es, pitch_mod, start_mod, halo);
   auto it = t.window_base.find(key);
   if (it == t.window_base.end()) {
     const int ntiles = static_cast<int>(hw.size() / p->nchans);
@@ -236,12 +242,12 @@ int device_window_base(dedisp_plan p, int device, int dms_per_tile, int samples,
     for (int tile = 0; tile < ntiles; ++tile)
       for (int c = 0; c < p->nchans; ++c) {
         const int2 w = hw[static_cast<size_t>(tile) * p->nchans + c];
-        const int mis = window_mis(c, pitch_mod, w.x, align);
-        // from the row's start rounded down to align: c*pitch mod align, then lo - mis
-        const int64_t start = (static_cast<int64_t>(c) * pitch_mod) % align + w.x - mis;
+        const int mis = window_mis(c, pitch_mod, start_mod, w.x, align);
+        // from the row's start rounded down to align: its phase, then lo - mis
+        const int64_t start = row_phase(c, pitch_mod, start_mod, align) + w.x - mis;
         // bytes the tile's reads reach: its samples, the delay spread, the
-        // start alignment and the halo lane's neighbour word
-        const int64_t bytes = es * (static_cast<int64_t>(w.y) - w.x + mis + samples) + 8;
+        // start alignment and the halo lane's neighbour read
+        const int64_t bytes = es * (static_cast<int64_t>(w.y) - w.x + mis + samples) + halo;
         uint32_t* e = base.data() + 2 * (static_cast<size_t>(tile) * stride + c);
         e[0] = static_cast<uint32_t>(es * start);
         e[1] = static_cast<uint32_t>((bytes + 1023) / 1024);
@@ -255,12 +261,12 @@ int device_window_base(dedisp_plan p, int device, int dms_per_tile, int samples,
   return DEDISP_OK;
 }
 
-int device_slot_pos(dedisp_plan p, int device, int dms_per_tile, int align, int es, int pitch_mod,
+int device_slot_pos(dedisp_plan p, int device, int dms_per_tile, int align, int es, int pitch_mod, int start_mod,
                     const int32_t** out) {
   const std::vector<int2>& hw = host_windows(p, dms_per_tile);
   std::lock_guard<std::mutex> g(p->mu);
   DeviceTables& t = p->dev[device];
-  const auto key = std::make_tuple(dms_per_tile, align, es, static_cast<int64_t>(pitch_mod));
+  const auto key = std::make_tuple(dms_per_tile, align, es, pitch_mod, start_mod);
   auto it = t.slot_pos.find(key);
   if (it == t.slot_pos.end()) {
     const int ntiles = static_cast<int>(hw.size() / p->nchans);
@@ -269,7 +275,7 @@ int device_slot_pos(dedisp_plan p, int device, int dms_per_tile, int align, int 
     for (int tile = 0; tile < ntiles; ++tile)
       for (int c = 0; c < p->nchans; ++c) {
         const int lo = hw[static_cast<size_t>(tile) * p->nchans + c].x;
-        const int mis = window_mis(c, pitch_mod, lo, align);
+        const int mis = window_mis(c, pitch_mod, start_mod, lo, align);
         const int32_t* row = p->shift.data() + static_cast<size_t>(c) * p->ndm;
         int32_t* dst = pos.data() + tile * stride + static_cast<size_t>(c) * dms_per_tile;
         for (int j = 0; j < dms_per_tile; ++j) {

@@ -2,20 +2,22 @@
 // concurrently on a pool of streams; each beam keeps its last max_shift input
 // samples on the device so that consecutive blocks overlap correctly.
 //
-// Per beam there are two device windows of [nchans][max_shift + B] samples in
-// staged form (8-bit samples widened to 16 bits, half to float, as the tiled
-// kernels read them) and one buffer for a raw block.  Block b of a beam is
-// copied as one contiguous transfer into the raw buffer; one kernel then
-// assembles window b%2: per channel the last max_shift samples of window
-// (b-1)%2 (zeros for the first block) followed by the new block widened.  The
-// de-dispersion kernel runs over that window directly (nsamp = B output
-// samples), so nothing is allocated or widened twice per block.  Every
-// operation of a beam goes to the same stream, so blocks of one beam run in
-// order and a window is not overwritten before the kernel two blocks back has
-// read it; different beams use different streams of the pool and overlap on
-// the device (copies of one beam under the kernels of others).
+// Per beam there is one ring buffer of [nchans][R] samples in staged form
+// (8-bit samples widened to 16 bits; half and float as they are) and one
+// buffer for a raw block.  Stream sample tau of a beam sits at ring position
+// (tau + H) mod R, H = max_shift rounded up to 8, R >= max_shift + B plus a
+// tile's overrun, a multiple of 8.  Block b of a beam is copied as one
+// contiguous transfer into the raw buffer; one kernel writes it into the ring
+// (widened where needed; nothing else is copied: the history stays where it
+// is), and the de-dispersion kernel reads the window of stream samples
+// [b*B - max_shift, (b+1)*B) straight from the ring, starting at position
+// (b*B + H - max_shift) mod R and wrapping at R.  Every operation of a beam
+// goes to the same stream, so blocks of one beam run in order and a block is
+// not written over history that an earlier kernel still reads; different
+// beams use different streams of the pool and overlap on the device (copies
+// of one beam under the kernels of others).
 //
-// Admission: a beam's windows and raw buffer are charged to the memory budget
+// Admission: a beam's ring and raw buffer are charged to the memory budget
 // when it is added; a request is charged its output (ndm*B values) and is
 // admitted while that fits the budget and fewer than max_inflight requests are
 // running.  Completion is recorded by a host callback enqueued after the
@@ -57,15 +59,22 @@ struct Request {
 struct Beam {
   dedisp_plan plan = nullptr;
   int64_t block = 0;  // B
-  int32_t tail = 0;   // max_shift
-  size_t es = 1;
-  void* win[2] = {nullptr, nullptr};  // staged windows
-  void* raw = nullptr;                // one raw block
+  int64_t ring = 0;   // R: samples per ring row
+  int64_t head = 0;   // H: ring position of stream sample 0
+  size_t es = 1;      // bytes per raw sample
+  void* rows = nullptr;  // ring rows [nchans][R], staged
+  void* raw = nullptr;   // one raw block
+  size_t ring_bytes = 0;
   size_t bytes = 0;
-  int64_t next = 0;        // index of the next block
+  int64_t next = 0;        // index of the next block since the history last restarted
   bool zero_tail = true;   // next block starts from a zero history
   int stream = 0;
 };
+
+// Ring length for a beam: the history and a block, plus the samples a tile
+// may read past the block (up to 4032 samples, its halo and the rounding of
+// its loads to 1 KB), a multiple of 8 samples.
+int64_t ring_samples(int64_t max_shift, int64_t block) { return (max_shift + block + 4608 + 7) / 8 * 8; }
 
 }  // namespace
 
@@ -153,22 +162,19 @@ extern "C" int dedisp_server_add_beam(dedisp_server s, dedisp_plan p, int64_t bl
   Beam b;
   b.plan = p;
   b.block = block_nsamp;
-  b.tail = p->max_shift;
+  b.ring = ring_samples(p->max_shift, block_nsamp);
+  b.head = (static_cast<int64_t>(p->max_shift) + 7) / 8 * 8;
   b.es = dedisp::dtype_size(p->dtype);
-  const size_t win_bytes = dedisp::staged_bytes(p, block_nsamp);
+  b.ring_bytes = static_cast<size_t>(p->nchans) * static_cast<size_t>(b.ring) * dedisp::staged_size(p->dtype);
   const size_t raw_bytes = static_cast<size_t>(p->nchans) * b.block * b.es;
-  b.bytes = 2 * win_bytes + raw_bytes;
+  b.bytes = b.ring_bytes + raw_bytes;
   std::lock_guard<std::mutex> g(s->mu);
   if (s->used.load() + b.bytes > s->budget) return DEDISP_ERR_AGAIN;
   hipError_t e = hipSetDevice(s->device);
-  if (e == hipSuccess) e = hipMalloc(&b.win[0], win_bytes);
-  if (e == hipSuccess) e = hipMalloc(&b.win[1], win_bytes);
+  if (e == hipSuccess) e = hipMalloc(&b.rows, b.ring_bytes);
   if (e == hipSuccess) e = hipMalloc(&b.raw, raw_bytes);
-  // the padding after the last channel row is never written again
-  if (e == hipSuccess) e = hipMemset(b.win[0], 0, win_bytes);
-  if (e == hipSuccess) e = hipMemset(b.win[1], 0, win_bytes);
   if (e != hipSuccess) {
-    for (void* x : {b.win[0], b.win[1], b.raw})
+    for (void* x : {b.rows, b.raw})
       if (x) (void)hipFree(x);
     return DEDISP_HIP_STATUS(e);
   }
@@ -216,16 +222,21 @@ extern "C" int dedisp_submit(dedisp_server s, int beam_id, const void* block, vo
   }
 
   hipStream_t st = s->streams[b.stream];
-  void* dst = b.win[b.next & 1];
-  const void* prev = b.win[(b.next + 1) & 1];
-  e = hipMemcpyAsync(b.raw, block, in_bytes, hipMemcpyDefault, st);
-  int status = DEDISP_HIP_STATUS(e);
+  int status = DEDISP_OK;
+  if (b.zero_tail) {  // a new history: zeros before the first block
+    b.next = 0;
+    status = DEDISP_HIP_STATUS(hipMemsetAsync(b.rows, 0, b.ring_bytes, st));
+  }
+  const int64_t first = (b.next % b.ring) * (b.block % b.ring) % b.ring;  // b*B mod R
+  if (status == DEDISP_OK) status = DEDISP_HIP_STATUS(hipMemcpyAsync(b.raw, block, in_bytes, hipMemcpyDefault, st));
   if (status == DEDISP_OK)
-    status = dedisp::assemble(p->dtype, prev, b.raw, dst, b.tail, b.block, p->nchans, b.zero_tail, st);
+    status = dedisp::ring_append(p->dtype, b.raw, b.rows, b.block, b.ring, (first + b.head) % b.ring, p->nchans, st);
   if (status == DEDISP_OK) {
     int v = p->variant.load();
     if (v < 0) v = dedisp::default_variant(p);
-    status = dedisp::launch_staged(p, v, dst, out_dev, b.block, st);
+    const int64_t start = (first + b.head - p->max_shift) % b.ring;
+    const dedisp::StagedRows rows{b.rows, b.ring, static_cast<int64_t>(p->nchans) * b.ring, start, b.ring};
+    status = dedisp::launch_rows(p, v, rows, out_dev, b.block, st);
   }
   if (status == DEDISP_OK) status = DEDISP_HIP_STATUS(hipLaunchHostFunc(st, on_done, r.get()));
   if (status != DEDISP_OK) {
@@ -306,7 +317,7 @@ extern "C" int dedisp_server_destroy(dedisp_server s) {
   int dev0 = -1;
   if (hipGetDevice(&dev0) == hipSuccess) (void)hipSetDevice(s->device);
   for (Beam& b : s->beams)
-    for (void* x : {b.win[0], b.win[1], b.raw})
+    for (void* x : {b.rows, b.raw})
       if (x) (void)hipFree(x);
   for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
   if (dev0 >= 0) (void)hipSetDevice(dev0);

@@ -185,7 +185,7 @@ def test_dm_grid_rejects(dd):
     assert dd.lib.dedisp_dm_grid(1.0, 4, None) == dd.DEDISP_ERR_INVALID_ARG
 
 
-@pytest.mark.parametrize("dtype,es,staged", [("u8", 1, 2), ("f16", 2, 4), ("f32", 4, 0)])
+@pytest.mark.parametrize("dtype,es,staged", [("u8", 1, 2), ("f16", 2, 0), ("f32", 4, 0)])
 def test_plan_footprint(dd, dtype, es, staged):
     band = wl.LOFAR
     dms = oracle.dm_grid(200.0, 64)

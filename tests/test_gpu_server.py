@@ -126,9 +126,9 @@ def test_admission_by_memory(dd):
     import torch
     band, dms, sh, m = beam_setup(7, 32, 16, 1.0, "f32", 512)
     plan = dd.Plan(32, band.f_top, band.df, band.tsamp, dms, "f32")
-    # two staged windows (padded to whole groups of 8 samples) and one raw block
-    total = 32 * (m + 512)
-    buf_bytes = 2 * ((total + 7) // 8 * 8) * 4 + 32 * 512 * 4
+    # one ring of max_shift + B + 4608 samples a row (rounded up to 8) and one raw block
+    ring = (m + 512 + 4608 + 7) // 8 * 8
+    buf_bytes = 32 * ring * 4 + 32 * 512 * 4
     # too small for the beam's buffers
     s = dd.dedisp_server_create(buf_bytes - 1, 4)
     try:
