@@ -169,6 +169,25 @@ int dedisp_autotune(dedisp_plan plan, int64_t nsamp, int *best_variant, double *
  */
 int dedisp_execute(dedisp_plan plan, const void *in_dev, void *out_dev, int64_t nsamp, void *stream);
 
+/*
+ * dedisp_execute without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and asynchrony as
+ * dedisp_execute.  The only workspace a launch needs (the widened copy of
+ * 8-bit input, staged_bytes of dedisp_plan_footprint) comes from a static
+ * device array of the library, 1 GiB on every device the library runs on,
+ * held until the process ends.  Requirements:
+ *   - staged_bytes <= 1 GiB, else DEDISP_ERR_INVALID_ARG (float and half
+ *     input need no workspace);
+ *   - the plan's device tables for this nsamp must already exist on the
+ *     current device (any earlier dedisp_execute or dedisp_autotune of the
+ *     plan with this nsamp on this device creates them), else
+ *     DEDISP_ERR_INVALID_ARG.
+ * Calls on one device share the array: two 8-bit calls that overlap in time
+ * on one device (different streams) race; order them on one stream.
+ */
+int dedisp_execute_static(dedisp_plan plan, const void *in_dev, void *out_dev, int64_t nsamp, void *stream);
+
 /* ------------------------------------------------------------- ingestion -- */
 
 /* Fields of a sigproc filterbank header that the search uses. */

@@ -140,8 +140,9 @@ struct dedisp_plan_s {
 
 namespace dedisp {
 
-// Device table of a plan on the current device (uploaded on first use).
-int device_tables(dedisp_plan p, int device, DeviceTables** out);
+// Device table of a plan on the current device (uploaded on first use; with
+// create = false a missing table is an error instead: nothing is allocated).
+int device_tables(dedisp_plan p, int device, DeviceTables** out, bool create = true);
 const std::vector<int2>& host_windows(dedisp_plan p, int dms_per_tile);
 // Staging tables of the tiled kernels for tiles of `dms_per_tile` trials,
 // windows aligned to `align` samples (16 bytes) and `es` bytes per staged
@@ -159,9 +160,9 @@ const std::vector<int2>& host_windows(dedisp_plan p, int dms_per_tile);
 // give the alignment of the trial).  Both depend on the row length and the
 // start only through pitch mod align and start mod align.
 int device_window_base(dedisp_plan p, int device, int dms_per_tile, int samples, int align, int es, int pitch_mod,
-                       int start_mod, int halo, const uint32_t** out);
+                       int start_mod, int halo, const uint32_t** out, bool create = true);
 int device_slot_pos(dedisp_plan p, int device, int dms_per_tile, int align, int es, int pitch_mod, int start_mod,
-                    const int32_t** out);
+                    const int32_t** out, bool create = true);
 
 // Kernel registry (kernels.hip).
 int variant_count();
@@ -177,7 +178,10 @@ int default_variant(dedisp_plan p);
 // Launch one plan's kernel over the whole problem.  8-bit input is widened
 // into `ws` (staged_bytes(p, nsamp) bytes) when given, else into a
 // stream-ordered allocation; float and half input are read as they are.
-int launch(dedisp_plan p, int variant, const void* in, void* out, int64_t nsamp, hipStream_t s, void* ws = nullptr);
+// With no_alloc, nothing is allocated: the 8-bit workspace must be given and
+// the plan's device tables must already exist (else DEDISP_ERR_INVALID_ARG).
+int launch(dedisp_plan p, int variant, const void* in, void* out, int64_t nsamp, hipStream_t s, void* ws = nullptr,
+           bool no_alloc = false);
 // The same over input rows already in staged form (8-bit widened to 16 bits,
 // float and half as they are), plain or ring rows.
 int launch_rows(dedisp_plan p, int variant, const StagedRows& rows, void* out, int64_t nsamp, hipStream_t s);
@@ -201,7 +205,11 @@ int widen_jobs(const WidenJob* jobs, int njobs, hipStream_t s);
 int tiled_args(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, TiledArgs* a, size_t* lds,
                int64_t* nblocks, int* threads);
 int tiled_args_rows(dedisp_plan p, int v, const StagedRows& rows, void* out, int64_t nsamp, TiledArgs* a,
-                    size_t* lds, int64_t* nblocks, int* threads);
+                    size_t* lds, int64_t* nblocks, int* threads, bool no_alloc = false);
+// The library's static device scratch (the allocation-free entry point's
+// 8-bit workspace): its address on the current device, and its size.
+int static_scratch(void** out);
+size_t static_scratch_bytes();
 // Hash of the variant registry and the kernels' generation (autotune keys).
 uint64_t registry_signature();
 // Everything a launch of variant v of plan p needs that must not happen inside

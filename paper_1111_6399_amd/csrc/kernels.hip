@@ -858,6 +858,14 @@ __global__ void reset_counter(unsigned long long* c) {
   if (threadIdx.x < kBatchCounters) c[threadIdx.x] = 0ull;
 }
 
+// ------------------------------------------------------ static scratch --
+
+// Workspace of the allocation-free entry point (dedisp_execute_static): the
+// widened copy of an 8-bit input.  Every device the library runs on holds one
+// until the process ends; calls on one device share it.
+constexpr size_t kStaticScratchBytes = static_cast<size_t>(1) << 30;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
 // ----------------------------------------------------------- registry --
 
 struct Variant {
@@ -992,12 +1000,13 @@ int launch_direct(dedisp_plan p, const DeviceTables* dt, const void* in, void* o
 }
 
 // A tiled variant over staged input.
-int launch_tiled(dedisp_plan p, int v, const StagedRows& rows, void* out, int64_t nsamp, hipStream_t s) {
+int launch_tiled(dedisp_plan p, int v, const StagedRows& rows, void* out, int64_t nsamp, hipStream_t s,
+                 bool no_alloc = false) {
   TiledArgs a;
   size_t lds = 0;
   int64_t nblocks = 0;
   int threads = 0;
-  int st = tiled_args_rows(p, v, rows, out, nsamp, &a, &lds, &nblocks, &threads);
+  int st = tiled_args_rows(p, v, rows, out, nsamp, &a, &lds, &nblocks, &threads, no_alloc);
   const void* fn = kVariants[v - 1].fn[stage_kind(p->dtype)];
   if (st == DEDISP_OK && lds > 64 * 1024) st = allow_large_lds(fn);
   if (st == DEDISP_OK) {
@@ -1027,12 +1036,13 @@ int keep_pool_memory(int dev) {
 
 }  // namespace
 
-int launch(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, hipStream_t s, void* ws_given) {
+int launch(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, hipStream_t s, void* ws_given,
+           bool no_alloc) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
   DeviceTables* dt = nullptr;
-  int st = device_tables(p, dev, &dt);
+  int st = device_tables(p, dev, &dt, !no_alloc);
   if (st != DEDISP_OK) return st;
   const int64_t pitch = nsamp + p->max_shift;
   const int64_t total = pitch * p->nchans;
@@ -1046,10 +1056,11 @@ int launch(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, hipSt
       default: return launch_direct<float>(p, dt, in, out, nsamp, pitch, 0, 0, s);
     }
   }
-  if (p->dtype != DEDISP_U8) return launch_tiled(p, v, StagedRows{in, pitch, total, 0, 0}, out, nsamp, s);
+  if (p->dtype != DEDISP_U8) return launch_tiled(p, v, StagedRows{in, pitch, total, 0, 0}, out, nsamp, s, no_alloc);
   // 8-bit input is widened into a workspace first: the caller's, else a
   // stream-ordered one
   void* ws = ws_given;
+  if (ws == nullptr && no_alloc) return DEDISP_ERR_INVALID_ARG;
   if (ws == nullptr) {
     st = keep_pool_memory(dev);
     if (st != DEDISP_OK) return st;
@@ -1057,7 +1068,8 @@ int launch(dedisp_plan p, int v, const void* in, void* out, int64_t nsamp, hipSt
     if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
   }
   st = widen(p->dtype, in, ws, total, s);
-  if (st == DEDISP_OK) st = launch_tiled(p, v, StagedRows{ws, pitch, widened_samples(total), 0, 0}, out, nsamp, s);
+  if (st == DEDISP_OK)
+    st = launch_tiled(p, v, StagedRows{ws, pitch, widened_samples(total), 0, 0}, out, nsamp, s, no_alloc);
   if (ws_given == nullptr) {
     const int st2 = DEDISP_HIP_STATUS(hipFreeAsync(ws, s));
     if (st == DEDISP_OK) st = st2;
@@ -1132,13 +1144,13 @@ int widen(int dtype, const void* in, void* ws, int64_t total, hipStream_t s) {
 }
 
 int tiled_args_rows(dedisp_plan p, int v, const StagedRows& rows, void* out, int64_t nsamp, TiledArgs* ap,
-                    size_t* lds_out, int64_t* nblocks_out, int* threads_out) {
+                    size_t* lds_out, int64_t* nblocks_out, int* threads_out, bool no_alloc) {
   if (v < 1 || v > kNumTiled) return DEDISP_ERR_INVALID_ARG;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
   DeviceTables* dt = nullptr;
-  int st = device_tables(p, dev, &dt);
+  int st = device_tables(p, dev, &dt, !no_alloc);
   if (st != DEDISP_OK) return st;
   const Variant& var = kVariants[v - 1];
   const int runs = slot_runs(p, var);
@@ -1153,10 +1165,10 @@ int tiled_args_rows(dedisp_plan p, int v, const StagedRows& rows, void* out, int
   const int start_mod = static_cast<int>(rows.start % align);
   const uint32_t* wbase = nullptr;
   st = device_window_base(p, dev, var.shape.dms(), var.shape.samples(), align, es, pitch_mod, start_mod,
-                          halo_bytes(p->dtype), &wbase);
+                          halo_bytes(p->dtype), &wbase, !no_alloc);
   if (st != DEDISP_OK) return st;
   const int32_t* spos = nullptr;
-  st = device_slot_pos(p, dev, var.shape.dms(), align, es, pitch_mod, start_mod, &spos);
+  st = device_slot_pos(p, dev, var.shape.dms(), align, es, pitch_mod, start_mod, &spos, !no_alloc);
   if (st != DEDISP_OK) return st;
   TiledArgs& a = *ap;
   a.in = rows.in;
@@ -1242,6 +1254,28 @@ int prepare(dedisp_plan p, int v, int64_t nsamp) {
   if (st != DEDISP_OK) return st;
   return allow_large_lds(kVariants[v - 1].fn[stage_kind(p->dtype)]);
 }
+
+int static_scratch(void** out) {
+  // the array's name is a host-side stand-in: its device address is looked
+  // up once per device (with that device current) and kept
+  static std::mutex mu;
+  static std::map<int, void*> ptrs;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return DEDISP_HIP_STATUS(e);
+  std::lock_guard<std::mutex> g(mu);
+  auto it = ptrs.find(dev);
+  if (it == ptrs.end()) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) return DEDISP_HIP_STATUS(e != hipSuccess ? e : hipErrorInvalidSymbol);
+    it = ptrs.emplace(dev, ptr).first;
+  }
+  *out = it->second;
+  return DEDISP_OK;
+}
+
+size_t static_scratch_bytes() { return kStaticScratchBytes; }
 
 const void* batch_kernel(int v, int kind) {
   return (v >= 1 && v <= kNumTiled && kind >= 0 && kind < 3) ? kVariants[v - 1].batch[kind] : nullptr;

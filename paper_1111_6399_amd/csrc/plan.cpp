@@ -168,8 +168,10 @@ const std::vector<int2>& host_windows(dedisp_plan p, int dms_per_tile) {
   return p->host_windows.emplace(dms_per_tile, std::move(w)).first->second;
 }
 
-int device_tables(dedisp_plan p, int device, DeviceTables** out) {
+int device_tables(dedisp_plan p, int device, DeviceTables** out, bool create) {
   std::lock_guard<std::mutex> g(p->mu);
+  auto found = p->dev.find(device);
+  if (!create && (found == p->dev.end() || found->second.shift == nullptr)) return DEDISP_ERR_INVALID_ARG;
   DeviceTables& t = p->dev[device];
   if (t.shift == nullptr) {
     // Rows padded to a multiple of 64 trials, pad entries repeat the last trial
@@ -227,12 +229,13 @@ inline int window_mis(int c, int pitch_mod, int start_mod, int lo, int align) {
 }  // namespace
 
 int device_window_base(dedisp_plan p, int device, int dms_per_tile, int samples, int align, int es, int pitch_mod,
-                       int start_mod, int halo, const uint32_t** out) {
+                       int start_mod, int halo, const uint32_t** out, bool create) {
   const std::vector<int2>& hw = host_windows(p, dms_per_tile);
   std::lock_guard<std::mutex> g(p->mu);
   DeviceTables& t = p->dev[device];
   const auto key = std::make_tuple(dms_per_tile, samples, align, es, pitch_mod, start_mod, halo);
   auto it = t.window_base.find(key);
+  if (it == t.window_base.end() && !create) return DEDISP_ERR_INVALID_ARG;
   if (it == t.window_base.end()) {
     const int ntiles = static_cast<int>(hw.size() / p->nchans);
     const int stride = p->nchans + kGeoPad;
@@ -262,12 +265,13 @@ int device_window_base(dedisp_plan p, int device, int dms_per_tile, int samples,
 }
 
 int device_slot_pos(dedisp_plan p, int device, int dms_per_tile, int align, int es, int pitch_mod, int start_mod,
-                    const int32_t** out) {
+                    const int32_t** out, bool create) {
   const std::vector<int2>& hw = host_windows(p, dms_per_tile);
   std::lock_guard<std::mutex> g(p->mu);
   DeviceTables& t = p->dev[device];
   const auto key = std::make_tuple(dms_per_tile, align, es, pitch_mod, start_mod);
   auto it = t.slot_pos.find(key);
+  if (it == t.slot_pos.end() && !create) return DEDISP_ERR_INVALID_ARG;
   if (it == t.slot_pos.end()) {
     const int ntiles = static_cast<int>(hw.size() / p->nchans);
     const size_t stride = static_cast<size_t>(p->nchans + kGeoPad) * dms_per_tile;
@@ -294,6 +298,25 @@ int device_slot_pos(dedisp_plan p, int device, int dms_per_tile, int align, int 
 }
 
 }  // namespace dedisp
+
+extern "C" int dedisp_execute_static(dedisp_plan p, const void* in, void* out, int64_t nsamp, void* stream) {
+  if (p == nullptr || nsamp < 0) return DEDISP_ERR_INVALID_ARG;
+  if (nsamp == 0) return DEDISP_OK;
+  if (in == nullptr || out == nullptr) return DEDISP_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(in) & 15) != 0 || (reinterpret_cast<uintptr_t>(out) & 3) != 0)
+    return DEDISP_ERR_INVALID_ARG;
+  if (nsamp > static_cast<int64_t>(INT32_MAX) - p->max_shift) return DEDISP_ERR_INVALID_ARG;
+  int v = p->variant.load();
+  if (v < 0) v = dedisp::default_variant(p);
+  void* ws = nullptr;
+  if (p->dtype == DEDISP_U8 && v > 0) {
+    // the widened copy goes to the library's static scratch
+    if (dedisp::staged_bytes(p, nsamp) > dedisp::static_scratch_bytes()) return DEDISP_ERR_INVALID_ARG;
+    const int st = dedisp::static_scratch(&ws);
+    if (st != DEDISP_OK) return st;
+  }
+  return dedisp::launch(p, v, in, out, nsamp, static_cast<hipStream_t>(stream), ws, true);
+}
 
 extern "C" int dedisp_execute(dedisp_plan p, const void* in, void* out, int64_t nsamp, void* stream) {
   if (p == nullptr || nsamp < 0) return DEDISP_ERR_INVALID_ARG;

@@ -55,6 +55,7 @@ _SIGS = {
     "dedisp_plan_get_variant": (_i, [_p, ctypes.POINTER(_i)]),
     "dedisp_autotune": (_i, [_p, _i64, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
     "dedisp_execute": (_i, [_p, _p, _p, _i64, _p]),
+    "dedisp_execute_static": (_i, [_p, _p, _p, _i64, _p]),
     "dedisp_detect": (_i, [_p, _p, _i64, _i, _d, _p, _p, _p, _p, _i, _p, _p]),
     "dedisp_sigproc_parse": (_i, [_p, ctypes.c_size_t, _p]),
     "dedisp_execute_cpu": (_i, [_p, _p, _p, _i64, _i, ctypes.POINTER(_i)]),
@@ -182,6 +183,10 @@ def dedisp_autotune(plan: int, nsamp: int):
 
 def dedisp_execute(plan: int, in_ptr: int, out_ptr: int, nsamp: int, stream=None) -> None:
     _check(lib.dedisp_execute(plan, in_ptr, out_ptr, int(nsamp), _stream(stream)), "dedisp_execute")
+
+
+def dedisp_execute_static(plan: int, in_ptr: int, out_ptr: int, nsamp: int, stream=None) -> None:
+    _check(lib.dedisp_execute_static(plan, in_ptr, out_ptr, int(nsamp), _stream(stream)), "dedisp_execute_static")
 
 
 # ------------------------------------------------------------------- host
