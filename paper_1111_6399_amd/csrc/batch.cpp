@@ -35,6 +35,8 @@
 
 namespace {
 
+constexpr int kBranches = 4;
+
 struct BatchGroup {
   int variant = -1;
   int kind = 0;                         // staging kind of its beams (dedisp::StageKind)
@@ -70,6 +72,12 @@ struct dedisp_batch_s {
   int h_half = 0;
   hipEvent_t h_done[2] = {nullptr, nullptr};
   hipStream_t capture = nullptr;
+  // graph branches: the group kernels and solo launches are captured on
+  // these, forked from and joined back to the capture stream, so that the
+  // graph runs them concurrently and one kernel's tail overlaps the others
+  hipStream_t branch[kBranches] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kBranches] = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<const void*> ins;
@@ -110,6 +118,14 @@ int free_device(dedisp_batch b) {
   for (auto& e : b->h_done)
     if (e) (void)hipEventDestroy(e);
   if (b->capture) (void)hipStreamDestroy(b->capture);
+  for (auto& x : b->branch)
+    if (x) (void)hipStreamDestroy(x);
+  for (auto& x : b->join_ev)
+    if (x) (void)hipEventDestroy(x);
+  if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+  for (auto& x : b->branch) x = nullptr;
+  for (auto& x : b->join_ev) x = nullptr;
+  b->fork_ev = nullptr;
   b->h_args = nullptr;
   b->h_done[0] = b->h_done[1] = nullptr;
   b->capture = nullptr;
@@ -301,6 +317,11 @@ int setup_device(dedisp_batch b, int dev, const void* const* ins, void* const* o
   for (auto& ev : b->h_done)
     if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return DEDISP_HIP_STATUS(e);
   if ((e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking)) != hipSuccess) return DEDISP_HIP_STATUS(e);
+  for (auto& x : b->branch)
+    if ((e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking)) != hipSuccess) return DEDISP_HIP_STATUS(e);
+  for (auto& x : b->join_ev)
+    if ((e = hipEventCreateWithFlags(&x, hipEventDisableTiming)) != hipSuccess) return DEDISP_HIP_STATUS(e);
+  if ((e = hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming)) != hipSuccess) return DEDISP_HIP_STATUS(e);
   b->device = dev;
   if (b->groups.empty()) return DEDISP_OK;
   std::vector<std::vector<int64_t>> ends;
@@ -353,10 +374,31 @@ int build_graph(dedisp_batch b, const void* const* ins, void* const* outs) {
     return DEDISP_HIP_STATUS(e);
   int st = DEDISP_OK;
   if (b->njobs > 0) st = dedisp::widen_jobs(b->d_jobs, b->njobs, b->capture);
-  for (size_t gi = 0; gi < b->groups.size() && st == DEDISP_OK; ++gi) {
+  // fork: branch k waits for the widening, then runs its share
+  if (st == DEDISP_OK) st = DEDISP_HIP_STATUS(hipEventRecord(b->fork_ev, b->capture));
+  for (int k = 0; k < kBranches && st == DEDISP_OK; ++k)
+    st = DEDISP_HIP_STATUS(hipStreamWaitEvent(b->branch[k], b->fork_ev, 0));
+  // the groups in order of their work (largest first), each on the branch
+  // with the least work so far; then the solo launches the same way
+  double load[kBranches] = {};
+  auto pick = [&load]() {
+    int k = 0;
+    for (int j = 1; j < kBranches; ++j)
+      if (load[j] < load[k]) k = j;
+    return k;
+  };
+  std::vector<size_t> gorder(b->groups.size());
+  std::iota(gorder.begin(), gorder.end(), size_t{0});
+  std::stable_sort(gorder.begin(), gorder.end(),
+                   [b](size_t x, size_t y) { return b->groups[x].work > b->groups[y].work; });
+  for (size_t n = 0; n < gorder.size() && st == DEDISP_OK; ++n) {
+    const size_t gi = gorder[n];
     BatchGroup& g = b->groups[gi];
+    const int k = pick();
+    load[k] += g.work;
+    hipStream_t bs = b->branch[k];
     void* rargs[] = {&g.d_counter};
-    e = hipLaunchKernel(dedisp::reset_kernel(), dim3(1), dim3(dedisp::reset_kernel_threads()), rargs, 0, b->capture);
+    e = hipLaunchKernel(dedisp::reset_kernel(), dim3(1), dim3(dedisp::reset_kernel_threads()), rargs, 0, bs);
     if (e == hipSuccess) {
       dedisp::BatchArgs ba;
       ba.beams = g.d_args;
@@ -365,13 +407,21 @@ int build_graph(dedisp_batch b, const void* const* ins, void* const* outs) {
       ba.n_items = g.n_items;
       ba.counter = g.d_counter;
       void* kargs[] = {&ba};
-      e = hipLaunchKernel(fns[gi], dim3(g.grid), dim3(g.threads), kargs, g.lds, b->capture);
+      e = hipLaunchKernel(fns[gi], dim3(g.grid), dim3(g.threads), kargs, g.lds, bs);
     }
     if (e != hipSuccess) st = DEDISP_HIP_STATUS(e);
   }
-  for (size_t k = 0; k < b->solo.size() && st == DEDISP_OK; ++k) {
-    const int i = b->solo[k];
-    st = dedisp::launch(b->plans[i], b->solo_variant[k], ins[i], outs[i], b->nsamps[i], b->capture, b->ws[i]);
+  for (size_t n = 0; n < b->solo.size() && st == DEDISP_OK; ++n) {
+    const int i = b->solo[n];
+    const int k = pick();
+    load[k] += beam_work(b, i);
+    st = dedisp::launch(b->plans[i], b->solo_variant[n], ins[i], outs[i], b->nsamps[i], b->branch[k], b->ws[i]);
+  }
+  // join every branch back into the capture stream
+  for (int k = 0; k < kBranches; ++k) {
+    hipError_t e1 = hipEventRecord(b->join_ev[k], b->branch[k]);
+    if (e1 == hipSuccess) e1 = hipStreamWaitEvent(b->capture, b->join_ev[k], 0);
+    if (e1 != hipSuccess && st == DEDISP_OK) st = DEDISP_HIP_STATUS(e1);
   }
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(b->capture, &g);

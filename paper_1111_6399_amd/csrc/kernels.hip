@@ -817,23 +817,29 @@ __global__ __launch_bounds__(64 * WD * WT) void dedisp_tiled(const TiledArgs a) 
 // kernel per staging kind, so that each carries the registers of one path
 // only.
 template <int KIND, int DW, int KS, int WD, int WT, int CG, int IW>
-__global__ __launch_bounds__(64 * WD * WT) void dedisp_batch_persistent(const BatchArgs b) {
-  __shared__ long long item_s;
+__global__ __launch_bounds__(64 * WD * WT) __attribute__((amdgpu_waves_per_eu(DW <= 2 ? 4 : 2)))
+void dedisp_batch_persistent(const BatchArgs b) {
+  __shared__ long long item_s[2];
   // Blocks run on XCD blockIdx.x mod 8.  Items go out in chunks of
   // kBatchChunk consecutive ones (neighbouring tiles of a beam, whose windows
   // overlap), chunk j to counter j mod nx: the workgroups of one XCD share a
   // counter, so a chunk stays in one L2, and every XCD gets the same mix of
-  // beams.  (With fewer than 8 workgroups, nx = the grid.)
+  // beams.  (With fewer than 8 workgroups, nx = the grid.)  The next item is
+  // claimed while the current one runs, so the counter's latency is off the
+  // path between items.
   const int nx = gridDim.x < 8 ? static_cast<int>(gridDim.x) : 8;
   const int xcd = static_cast<int>(blockIdx.x) % nx;
-  for (;;) {
-    if (threadIdx.x == 0) item_s = static_cast<long long>(atomicAdd(b.counter + xcd, 1ull));
-    lds_barrier();
+  if (threadIdx.x == 0) item_s[0] = static_cast<long long>(atomicAdd(b.counter + xcd, 1ull));
+  lds_barrier();
+  for (int cur = 0;; cur ^= 1) {
     const long long k =
-        static_cast<long long>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(item_s)))) |
-        (static_cast<long long>(__builtin_amdgcn_readfirstlane(static_cast<int>(item_s >> 32))) << 32);
+        static_cast<long long>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(item_s[cur])))) |
+        (static_cast<long long>(__builtin_amdgcn_readfirstlane(static_cast<int>(item_s[cur] >> 32))) << 32);
     const long long item = (k / kBatchChunk) * (nx * kBatchChunk) + xcd * kBatchChunk + k % kBatchChunk;
     if (item >= b.n_items) return;  // the counter's later items are further on
+    // claimed now, stored at the end of the item: its latency overlaps the tile
+    unsigned long long next = 0;
+    if (threadIdx.x == 0) next = atomicAdd(b.counter + xcd, 1ull);
     typedef __attribute__((address_space(4))) const int64_t cint64;
     typedef __attribute__((address_space(4))) const TiledArgs ctargs;
     cint64* ends = (cint64*)(b.item_end);
@@ -850,7 +856,9 @@ __global__ __launch_bounds__(64 * WD * WT) void dedisp_batch_persistent(const Ba
     const int dm_tile = __builtin_amdgcn_readfirstlane((g % a.n_dm_groups) * a.gd + i % a.gd);
     const int t_tile = __builtin_amdgcn_readfirstlane((g / a.n_dm_groups) * a.gt + i / a.gd);
     if (dm_tile < a.n_dm_tiles && t_tile < a.n_t_tiles) tile_dma<KIND, DW, KS, WD, WT, CG, IW>(a, dm_tile, t_tile);
-    lds_barrier();  // every wave is done with this item's LDS before the next
+    if (threadIdx.x == 0) item_s[cur ^ 1] = static_cast<long long>(next);
+    // every wave is done with this item's LDS, and the next item's index is visible
+    lds_barrier();
   }
 }
 
