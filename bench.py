@@ -291,7 +291,9 @@ def run_batch(args) -> dict:
     }
 
 
-P99_TARGET_S = 0.5  # served latency target: a quarter of a 2.1 s MeerKAT block
+# served latency targets: a quarter and a half of a 2.1 s MeerKAT block
+P99_TARGET_S = 0.5
+P99_TARGETS_S = (0.5, 1.0)
 
 
 def served_compare(nbeams, rate_x, warmup_s, duration, inflight=8, budget_gb=128.0, pool_n=4, max_backlog=256,
@@ -409,9 +411,10 @@ def served_compare(nbeams, rate_x, warmup_s, duration, inflight=8, budget_gb=128
             % (label, n, 1e3 * (p50 or 0), 1e3 * (p99 or 0), thr or 0, backlog[0], 1e3 * (sub_mean or 0),
                1e3 * (sub_max or 0), " (OVERLOADED: arrivals stopped)" if backlog[1] else ""))
         sustained = bool(n > 1 and not backlog[1] and p99 is not None and p99 <= P99_TARGET_S)
+        within = {str(t): bool(n > 1 and not backlog[1] and p99 is not None and p99 <= t) for t in P99_TARGETS_S}
         return {"rate_x_realtime": rate_x, "blocks": n, "p50_s": p50, "p99_s": p99, "value": thr,
                 "max_backlog": backlog[0], "overloaded": backlog[1], "sustained_at_p99_target": sustained,
-                "submit_mean_s": sub_mean, "submit_max_s": sub_max}
+                "p99_within": within, "submit_mean_s": sub_mean, "submit_max_s": sub_max}
 
     server = dd.dedisp_server_create(int(budget_gb * (1 << 30)), inflight)
     try:
@@ -469,10 +472,11 @@ def run_served(args) -> dict:
         served, plain, plan = served_compare(args.beams, r, args.warmup_s, args.duration, args.inflight,
                                              args.budget_gb, args.pool, args.max_backlog, args.variant, plan)
         rows.append({"rate_x_realtime": r, "served": served, "plain_fifo": plain})
-    best = {form: max([row["rate_x_realtime"] for row in rows if row[form]["sustained_at_p99_target"]],
-                      default=None) for form in ("served", "plain_fifo")}
-    log("highest rate sustained with p99 <= %.0f ms: served %s, plain %s"
-        % (1e3 * P99_TARGET_S, best["served"], best["plain_fifo"]))
+    best = {str(t): {form: max([row["rate_x_realtime"] for row in rows if row[form]["p99_within"][str(t)]],
+                               default=None) for form in ("served", "plain_fifo")} for t in P99_TARGETS_S}
+    for t in P99_TARGETS_S:
+        log("highest rate sustained with p99 <= %.0f ms: served %s, plain %s"
+            % (1e3 * t, best[str(t)]["served"], best[str(t)]["plain_fifo"]))
     top = rows[0]["served"]
     from paper_1111_6399_amd import workloads as wl
     w = wl.meerkat_block(32768)
@@ -486,7 +490,7 @@ def run_served(args) -> dict:
         "config": {"workload": "served-meerkat", "nbeams": args.beams, "block": 32768, "ndm": w.ndm,
                    "nchans": w.band.nchans, "max_shift": plan.max_shift, "rates_x_realtime": rates,
                    "duration_s": args.duration, "inflight": args.inflight, "variant": plan.variant},
-        "p99_target_s": P99_TARGET_S, "sweep": rows, "highest_sustained_rate_x": best,
+        "p99_targets_s": list(P99_TARGETS_S), "sweep": rows, "highest_sustained_rate_x": best,
         "rtf": None if not value else value / work * 32768 * w.band.tsamp,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TADDS, "unit": "Tadd/s",
                      "frac": achieved / ALU_PEAK_TADDS, "traffic": None},
