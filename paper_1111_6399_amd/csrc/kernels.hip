@@ -90,7 +90,6 @@ __global__ __launch_bounds__(256) void dedisp_direct(const In* __restrict__ in, 
 
 // ------------------------------------------------------------- tiled --
 
-typedef int v4i __attribute__((ext_vector_type(4)));
 typedef uint32_t v2u __attribute__((ext_vector_type(2)));
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
@@ -331,60 +330,37 @@ __device__ __forceinline__ void wait_vm() {
   asm volatile("s_waitcnt vmcnt(%0)" ::"i"(N) : "memory");
 }
 
-// Buffer descriptor words for `bytes` bytes from `p` (raw buffer, range
-// checked: reads past the end return zero without touching memory; more than
-// 2^32 - 1 bytes are clamped to that).
-__device__ __forceinline__ v4i buffer_words(const void* p, int64_t bytes) {
+// Buffer resource for `bytes` bytes from `p` (raw buffer, range checked: reads
+// past the end return zero without touching memory; more than 2^32 - 1 bytes
+// are clamped to that).  The address and size are wave-uniform by construction;
+// taking them through readfirstlane lets the compiler see that and keep the
+// resource in scalar registers.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, int64_t bytes) {
   const uint64_t a = reinterpret_cast<uint64_t>(p);
   const uint32_t n = bytes >= 0xffffffffll ? 0xffffffffu : static_cast<uint32_t>(bytes < 0 ? 0 : bytes);
-  v4i w;  // wave-uniform by construction; made explicit for the scalar operands of inline assembly
-  w.x = __builtin_amdgcn_readfirstlane(static_cast<int>(a & 0xffffffffu));
-  w.y = __builtin_amdgcn_readfirstlane(static_cast<int>((a >> 32) & 0xffffu));
-  w.z = __builtin_amdgcn_readfirstlane(static_cast<int>(n));
-  w.w = 0x00020000;
-  return w;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<int>(a & 0xffffffffu));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<int>(a >> 32));
+  const int nu = __builtin_amdgcn_readfirstlane(static_cast<int>(n));
+  void* base = reinterpret_cast<void*>((static_cast<uint64_t>(hi) << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(base, 0, nu, 0x00020000);
 }
 
 // K runs of 1 KB from the buffer straight into LDS: run m takes 16 bytes per
 // lane from byte offset voff + 1024*m to LDS byte lds + 1024*m + 16*lane (the
 // instruction's immediate offset moves both addresses, so the runs share one
-// M0 and one offset register).
+// M0 value, which the compiler sets, and one offset register).
 template <int K>
-__device__ __forceinline__ void lds_dma_runs(uint32_t lds, uint32_t voff, const v4i& rs) {
+__device__ __forceinline__ void lds_dma_runs(uint32_t lds, uint32_t voff, __amdgpu_buffer_rsrc_t r) {
   static_assert(K >= 1 && K <= 4, "immediate offsets stay below 4 KB");
-  if constexpr (K == 1)
-    asm volatile("s_mov_b32 m0, %[lds]\n\ts_nop 0\n\t"
-                 "buffer_load_dwordx4 %[vo], %[rs], 0 offen lds"
-                 :
-                 : [lds] "s"(lds), [vo] "v"(voff), [rs] "s"(rs)
-                 : "memory", "m0");
-  else if constexpr (K == 2)
-    asm volatile("s_mov_b32 m0, %[lds]\n\ts_nop 0\n\t"
-                 "buffer_load_dwordx4 %[vo], %[rs], 0 offen lds\n\t"
-                 "buffer_load_dwordx4 %[vo], %[rs], 0 offen offset:1024 lds"
-                 :
-                 : [lds] "s"(lds), [vo] "v"(voff), [rs] "s"(rs)
-                 : "memory", "m0");
-  else if constexpr (K == 3)
-    asm volatile("s_mov_b32 m0, %[lds]\n\ts_nop 0\n\t"
-                 "buffer_load_dwordx4 %[vo], %[rs], 0 offen lds\n\t"
-                 "buffer_load_dwordx4 %[vo], %[rs], 0 offen offset:1024 lds\n\t"
-                 "buffer_load_dwordx4 %[vo], %[rs], 0 offen offset:2048 lds"
-                 :
-                 : [lds] "s"(lds), [vo] "v"(voff), [rs] "s"(rs)
-                 : "memory", "m0");
-  else
-    asm volatile("s_mov_b32 m0, %[lds]\n\ts_nop 0\n\t"
-                 "buffer_load_dwordx4 %[vo], %[rs], 0 offen lds\n\t"
-                 "buffer_load_dwordx4 %[vo], %[rs], 0 offen offset:1024 lds\n\t"
-                 "buffer_load_dwordx4 %[vo], %[rs], 0 offen offset:2048 lds\n\t"
-                 "buffer_load_dwordx4 %[vo], %[rs], 0 offen offset:3072 lds"
-                 :
-                 : [lds] "s"(lds), [vo] "v"(voff), [rs] "s"(rs)
-                 : "memory", "m0");
+  __attribute__((address_space(3))) void* dst =
+      (__attribute__((address_space(3))) void*)(static_cast<uintptr_t>(lds));
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, dst, 16, voff, 0, 0, 0);
+  if constexpr (K >= 2) __builtin_amdgcn_raw_ptr_buffer_load_lds(r, dst, 16, voff, 0, 1024, 0);
+  if constexpr (K >= 3) __builtin_amdgcn_raw_ptr_buffer_load_lds(r, dst, 16, voff, 0, 2048, 0);
+  if constexpr (K >= 4) __builtin_amdgcn_raw_ptr_buffer_load_lds(r, dst, 16, voff, 0, 3072, 0);
 }
 
-__device__ __forceinline__ void lds_dma_k(int k, uint32_t lds, uint32_t voff, const v4i& rs) {
+__device__ __forceinline__ void lds_dma_k(int k, uint32_t lds, uint32_t voff, __amdgpu_buffer_rsrc_t rs) {
   if (k >= 4)
     lds_dma_runs<4>(lds, voff, rs);
   else if (k == 3)
@@ -526,7 +502,7 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
     if (c < nchans) {
       if (gq >= IW || 4 * gq >= runs) return;
       const int64_t rb = row_base(c);
-      const v4i rs = buffer_words(static_cast<const char*>(a.in) + rb, ring ? static_cast<int64_t>(ring)
+      const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(static_cast<const char*>(a.in) + rb, ring ? static_cast<int64_t>(ring)
                                                                              : a.total16 * ES - rb);
       uint32_t lds = __builtin_amdgcn_readfirstlane(lds0 + slot + 4096u * gq);
       uint32_t u = wbase + t0b + 4096u * gq;  // wave-uniform byte offset of the chunk in the row
