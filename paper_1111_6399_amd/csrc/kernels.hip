@@ -242,6 +242,10 @@ __device__ __forceinline__ void lds_wait() {
   M(0, 1, 2, 3, 18, 19, 16, 17) M(4, 5, 6, 7, 20, 21, 16, 17) M(8, 9, 10, 11, 22, 23, 16, 17) \
       M(12, 13, 14, 15, 24, 25, 16, 17)
 #define DD_H2ALL(M) M(0, 1, 2, 3, 10, 11, 8, 9) M(4, 5, 6, 7, 12, 13, 8, 9)
+#define DD_H8ALL(M) M(0, 1, 2, 3, 34, 35, 32, 33) M(4, 5, 6, 7, 36, 37, 32, 33) M(8, 9, 10, 11, 38, 39, 32, 33) M(12, 13, 14, 15, 40, 41, 32, 33) M(16, 17, 18, 19, 42, 43, 32, 33) M(20, 21, 22, 23, 44, 45, 32, 33) M(24, 25, 26, 27, 46, 47, 32, 33) M(28, 29, 30, 31, 48, 49, 32, 33)
+// 8-bit pairs, 8 reads: e = %0-15, o = %16-31, reads %32-47
+#define DD_U8E(F) F(0, 1, 32, 33) F(2, 3, 34, 35) F(4, 5, 36, 37) F(6, 7, 38, 39) F(8, 9, 40, 41) F(10, 11, 42, 43) F(12, 13, 44, 45) F(14, 15, 46, 47)
+#define DD_U8O(F) F(16, 17, 32, 33) F(18, 19, 34, 35) F(20, 21, 36, 37) F(22, 23, 38, 39) F(24, 25, 40, 41) F(26, 27, 42, 43) F(28, 29, 44, 45) F(30, 31, 46, 47)
 
 template <int N>
 struct TrialAdds;
@@ -286,6 +290,39 @@ struct TrialAdds<4> {
                    "+v"(o[6]), "+v"(o[7])
                  : "v"(v[0].x), "v"(v[0].y), "v"(v[1].x), "v"(v[1].y), "v"(v[2].x), "v"(v[2].y), "v"(v[3].x),
                    "v"(v[3].y), "s"(p)
+                 : "scc");
+  }
+};
+
+// Eight reads a block (16-bit staging, one trial a wave): twice the adds of
+// four behind one scalar branch.
+template <>
+struct TrialAdds<8> {
+  // a[0..31] += the halves of 8 64-bit reads
+  static __device__ __forceinline__ void f16(float* x, const v2u (&v)[8], int p) {
+    uint32_t t, u;
+    asm volatile(DD_BR4(50, 1, 2, DD_H8ALL(DD_H4_0), DD_H8ALL(DD_H4_2), DD_H8ALL(DD_H4_1), DD_H8ALL(DD_H4_3))
+                 : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]),
+                   "+v"(x[7]), "+v"(x[8]), "+v"(x[9]), "+v"(x[10]), "+v"(x[11]), "+v"(x[12]), "+v"(x[13]),
+                   "+v"(x[14]), "+v"(x[15]), "+v"(x[16]), "+v"(x[17]), "+v"(x[18]), "+v"(x[19]), "+v"(x[20]),
+                   "+v"(x[21]), "+v"(x[22]), "+v"(x[23]), "+v"(x[24]), "+v"(x[25]), "+v"(x[26]), "+v"(x[27]),
+                   "+v"(x[28]), "+v"(x[29]), "+v"(x[30]), "+v"(x[31]), "=&v"(t), "=&v"(u)
+                 : "v"(v[0].x), "v"(v[0].y), "v"(v[1].x), "v"(v[1].y), "v"(v[2].x), "v"(v[2].y), "v"(v[3].x),
+                   "v"(v[3].y), "v"(v[4].x), "v"(v[4].y), "v"(v[5].x), "v"(v[5].y), "v"(v[6].x), "v"(v[6].y),
+                   "v"(v[7].x), "v"(v[7].y), "s"(p)
+                 : "scc");
+  }
+  // e[0..15], o[0..15]
+  static __device__ __forceinline__ void u8(uint32_t* e, uint32_t* o, const v2u (&v)[8], int p) {
+    asm volatile(DD_BR4(48, 1, 2, DD_U8E(DD_U_AL2), DD_U8E(DD_U_SH2), DD_U8O(DD_U_AL2), DD_U8O(DD_U_SH2))
+                 : "+v"(e[0]), "+v"(e[1]), "+v"(e[2]), "+v"(e[3]), "+v"(e[4]), "+v"(e[5]), "+v"(e[6]),
+                   "+v"(e[7]), "+v"(e[8]), "+v"(e[9]), "+v"(e[10]), "+v"(e[11]), "+v"(e[12]), "+v"(e[13]),
+                   "+v"(e[14]), "+v"(e[15]), "+v"(o[0]), "+v"(o[1]), "+v"(o[2]), "+v"(o[3]), "+v"(o[4]),
+                   "+v"(o[5]), "+v"(o[6]), "+v"(o[7]), "+v"(o[8]), "+v"(o[9]), "+v"(o[10]), "+v"(o[11]),
+                   "+v"(o[12]), "+v"(o[13]), "+v"(o[14]), "+v"(o[15])
+                 : "v"(v[0].x), "v"(v[0].y), "v"(v[1].x), "v"(v[1].y), "v"(v[2].x), "v"(v[2].y), "v"(v[3].x),
+                   "v"(v[3].y), "v"(v[4].x), "v"(v[4].y), "v"(v[5].x), "v"(v[5].y), "v"(v[6].x), "v"(v[6].y),
+                   "v"(v[7].x), "v"(v[7].y), "s"(p)
                  : "scc");
   }
 };
@@ -871,6 +908,17 @@ struct Variant {
          reinterpret_cast<const void*>(&dedisp_batch_persistent<kStagePairs, DW, KS, WD, WT, CG, IW>)}    \
   }
 
+// Variants for the 16-bit staging kinds only (halves and 8-bit pairs): no
+// float kernel.
+#define DEDISP_VARIANT_16(DW, KS, WD, WT, CG, IW)                                                         \
+  Variant {                                                                                               \
+    TileShape{DW, KS, WD, WT}, CG, IW,                                                                    \
+        {nullptr, reinterpret_cast<const void*>(&dedisp_tiled<kStageHalves, DW, KS, WD, WT, CG, IW>),     \
+         reinterpret_cast<const void*>(&dedisp_tiled<kStagePairs, DW, KS, WD, WT, CG, IW>)},              \
+        {nullptr, reinterpret_cast<const void*>(&dedisp_batch_persistent<kStageHalves, DW, KS, WD, WT, CG, IW>), \
+         reinterpret_cast<const void*>(&dedisp_batch_persistent<kStagePairs, DW, KS, WD, WT, CG, IW>)}    \
+  }
+
 // The last argument is the number of waves of a group that share a window's
 // loads (4 KB each in turn): a single loading wave is late to every stage's
 // barrier by the time it spends issuing, so groups of 4 or 8 waves share the
@@ -887,12 +935,16 @@ const Variant kVariants[] = {
     DEDISP_VARIANT(4, 8, 8, 1, 2, 4),  // 32 x 1008, 512 threads
     DEDISP_VARIANT(2, 4, 8, 2, 2, 2),  // 16 x 1008, 1024 threads
     DEDISP_VARIANT(2, 8, 8, 1, 8, 1),  // 16 x 1008, 512 threads, 8 channels per stage (small delay spreads)
+    // one trial a wave, 2016 samples, eight reads a block (16-bit staging only)
+    DEDISP_VARIANT_16(1, 16, 8, 1, 4, 2),   // 8 x 2016, 512 threads, 4 channels per stage
+    DEDISP_VARIANT_16(1, 16, 8, 1, 8, 1),   // 8 x 2016, 512 threads, 8 channels per stage
+    DEDISP_VARIANT_16(1, 16, 16, 1, 8, 2),  // 16 x 2016, 1024 threads, 8 channels per stage
 };
 constexpr int kNumTiled = sizeof(kVariants) / sizeof(kVariants[0]);
 
 // Bumped whenever the tile kernels change in a way that can change which
 // variant is fastest (the autotuner's cache keys carry it).
-constexpr int kKernelGeneration = 2;
+constexpr int kKernelGeneration = 3;
 
 constexpr size_t kMaxLds = 160 * 1024;
 
@@ -956,11 +1008,11 @@ int tiled_per_cu(dedisp_plan p, int v) {
 bool variant_fits(dedisp_plan p, int v) {
   if (v == 0) return true;
   if (v < 0 || v > kNumTiled) return false;
-  return slot_runs(p, kVariants[v - 1]) > 0;
+  return kVariants[v - 1].fn[stage_kind(p->dtype)] != nullptr && slot_runs(p, kVariants[v - 1]) > 0;
 }
 
 int default_variant(dedisp_plan p) {
-  static const int order[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11};
+  static const int order[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14};
   for (int v : order)
     if (v <= kNumTiled && variant_fits(p, v)) return v;
   return 0;
@@ -1137,6 +1189,7 @@ int tiled_args_rows(dedisp_plan p, int v, const StagedRows& rows, void* out, int
   int st = device_tables(p, dev, &dt, !no_alloc);
   if (st != DEDISP_OK) return st;
   const Variant& var = kVariants[v - 1];
+  if (var.fn[stage_kind(p->dtype)] == nullptr) return DEDISP_ERR_INVALID_ARG;  // no kernel for this staging kind
   const int runs = slot_runs(p, var);
   if (runs == 0) return DEDISP_ERR_INVALID_ARG;
   // the tiled kernels address each row with 32-bit byte offsets
@@ -1236,7 +1289,9 @@ int prepare(dedisp_plan p, int v, int64_t nsamp) {
   const int32_t* spos = nullptr;
   st = device_slot_pos(p, dev, dms, align, es, static_cast<int>(pitch % align), 0, &spos);
   if (st != DEDISP_OK) return st;
-  return allow_large_lds(kVariants[v - 1].fn[stage_kind(p->dtype)]);
+  const void* fn = kVariants[v - 1].fn[stage_kind(p->dtype)];
+  if (fn == nullptr) return DEDISP_ERR_INVALID_ARG;
+  return allow_large_lds(fn);
 }
 
 int static_scratch(void** out) {
