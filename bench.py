@@ -240,11 +240,12 @@ def run_batch(args) -> dict:
         wall = time.perf_counter() - t0
         batch_ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
         variant = dd.dedisp_batch_get_variant(batch)
+        layout = dd.dedisp_batch_get_layout(batch)
     finally:
         dd.dedisp_batch_destroy(batch)
     ms_per_step = wall * 1e3 / args.steps
-    log("batched graph: %.3f ms/step wall, %.3f ms median (variant %d, %d items, %d workgroups)"
-        % (ms_per_step, batch_ms, variant, items, groups))
+    log("batched graph: %.3f ms/step wall, %.3f ms median (variant %d, layout %d, %d items, %d workgroups)"
+        % (ms_per_step, batch_ms, variant, layout, items, groups))
 
     # spot check: two beams, one of each dtype, a few trials each
     ok = True
@@ -281,7 +282,8 @@ def run_batch(args) -> dict:
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+u8", "data": "synthetic",
         "config": {"workload": "batch-32-beams", "nbeams": len(beams), "adds": adds, "in_bytes": in_bytes,
-                   "out_bytes": out_bytes, "variant": variant, "work_items": items, "workgroups": groups},
+                   "out_bytes": out_bytes, "variant": variant, "layout": layout, "work_items": items,
+                   "workgroups": groups},
         "rtf": sum(w.nsamp * w.band.tsamp for w in beams) / (batch_ms * 1e-3),
         "parity_spot_check": ok,
         "plain_per_beam": {"ms": plain_ms, "value": adds / (plain_ms * 1e-3)},

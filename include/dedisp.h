@@ -327,14 +327,26 @@ int dedisp_batch_info(dedisp_batch batch, int64_t *work_items, int *workgroups);
 int dedisp_batch_get_variant(dedisp_batch batch, int *variant);
 int dedisp_batch_set_variant(dedisp_batch batch, int variant);
 
+/* How the graph spreads its kernels over its four branches (concurrent
+ * streams forked from and joined to the launch stream): 0 each on the branch
+ * with the least work so far (largest first), 1 all on one branch in beam
+ * order (the plain per-beam sequence without its launch overheads), 2 one
+ * branch for the float beams and one for the 16-bit (half and 8-bit) beams.
+ * Setting a layout outside 0-2 is an invalid argument; setting rebuilds the
+ * graph on the next execute and synchronises the batch's device;
+ * dedisp_batch_set_variant resets it to 0. */
+int dedisp_batch_get_layout(dedisp_batch batch, int *layout);
+int dedisp_batch_set_layout(dedisp_batch batch, int layout);
+
 /* Time the batch with every tile variant that fits any of its beams; with
  * 8-bit and float beams mixed, also each variant for the 8-bit beams with the
  * float beams' held, then each for the float beams (the two kinds run as
  * separate persistent kernels); the split that follows each plan's own
  * variant (set or tuned with dedisp_autotune); and every beam launched on its
- * own with its plan's variant, the launches captured in the graph.  Keeps the
- * fastest; best_variant is then the variant of the persistent kernel that
- * carries the most work (-1 if the per-beam launches won).  Synchronises the
+ * own with its plan's variant, the launches captured in the graph in each
+ * layout (dedisp_batch_get_layout).  Keeps the fastest; best_variant is then
+ * the variant of the persistent kernel that carries the most work (-1 if the
+ * per-beam launches won).  Synchronises the
  * stream.  The outputs are overwritten (with correct results).  best_ms may
  * be NULL. */
 int dedisp_batch_autotune(dedisp_batch batch, const void *const *ins, void *const *outs, void *stream,

@@ -59,6 +59,11 @@ struct dedisp_batch_s {
   std::vector<int64_t> nsamps;
   int nbeams = 0;
   int variant = -1;  // variant of the group that carries the most work
+  // how the graph spreads its launches over the branches: 0 each on the
+  // branch with the least work so far, 1 all on one branch in order (the
+  // plain sequence, without its launch overheads), 2 one branch per staging
+  // kind (float and 16-bit beams side by side)
+  int layout = 0;
   std::vector<BatchGroup> groups;
   std::vector<int> solo;  // beams launched on their own
   std::vector<int> solo_variant;
@@ -381,7 +386,9 @@ int build_graph(dedisp_batch b, const void* const* ins, void* const* outs) {
   // the groups in order of their work (largest first), each on the branch
   // with the least work so far; then the solo launches the same way
   double load[kBranches] = {};
-  auto pick = [&load]() {
+  auto pick = [&load, b](int kind) {
+    if (b->layout == 1) return 0;
+    if (b->layout == 2) return kind == dedisp::kStageFloat ? 0 : 1;
     int k = 0;
     for (int j = 1; j < kBranches; ++j)
       if (load[j] < load[k]) k = j;
@@ -394,7 +401,7 @@ int build_graph(dedisp_batch b, const void* const* ins, void* const* outs) {
   for (size_t n = 0; n < gorder.size() && st == DEDISP_OK; ++n) {
     const size_t gi = gorder[n];
     BatchGroup& g = b->groups[gi];
-    const int k = pick();
+    const int k = pick(g.kind);
     load[k] += g.work;
     hipStream_t bs = b->branch[k];
     void* rargs[] = {&g.d_counter};
@@ -413,7 +420,7 @@ int build_graph(dedisp_batch b, const void* const* ins, void* const* outs) {
   }
   for (size_t n = 0; n < b->solo.size() && st == DEDISP_OK; ++n) {
     const int i = b->solo[n];
-    const int k = pick();
+    const int k = pick(dedisp::stage_kind(b->plans[i]->dtype));
     load[k] += beam_work(b, i);
     st = dedisp::launch(b->plans[i], b->solo_variant[n], ins[i], outs[i], b->nsamps[i], b->branch[k], b->ws[i]);
   }
@@ -627,18 +634,24 @@ extern "C" int dedisp_batch_autotune(dedisp_batch b, const void* const* ins, voi
       }
     }
   }
-  if (st == DEDISP_OK) {
+  // the per-beam launches, in each layout of the branches
+  int best_layout = 0, solo_layout = -1;
+  for (int layout = 0; layout < 3 && st == DEDISP_OK; ++layout) {
     (void)hipStreamSynchronize(stream);
     free_device(b);
     assign_solo(b);
+    b->layout = layout;
     double t = 0.0;
     st = time_split(&t);
     if (st == DEDISP_OK && t < best_t) {
       best_t = t;
       best_solo = true;
       best_own = kinds = false;
+      solo_layout = layout;
     }
   }
+  if (best_solo) best_layout = solo_layout;
+  b->layout = 0;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != DEDISP_OK) return st;
@@ -652,8 +665,26 @@ extern "C" int dedisp_batch_autotune(dedisp_batch b, const void* const* ins, voi
     assign_kinds(b, best8, bestf);
   else
     assign(b, best);
+  b->layout = best_layout;
   *best_variant = b->variant;
   if (best_ms) *best_ms = best_t;
+  return DEDISP_OK;
+}
+
+extern "C" int dedisp_batch_get_layout(dedisp_batch b, int* layout) {
+  if (b == nullptr || layout == nullptr) return DEDISP_ERR_INVALID_ARG;
+  *layout = b->layout;
+  return DEDISP_OK;
+}
+
+extern "C" int dedisp_batch_set_layout(dedisp_batch b, int layout) {
+  if (b == nullptr || layout < 0 || layout > 2) return DEDISP_ERR_INVALID_ARG;
+  int dev0 = -1;
+  if (b->device >= 0 && hipGetDevice(&dev0) == hipSuccess) (void)hipSetDevice(b->device);
+  if (b->device >= 0) (void)hipDeviceSynchronize();
+  free_graph(b);
+  if (dev0 >= 0) (void)hipSetDevice(dev0);
+  b->layout = layout;
   return DEDISP_OK;
 }
 
@@ -670,6 +701,7 @@ extern "C" int dedisp_batch_set_variant(dedisp_batch b, int variant) {
   if (b->device >= 0) (void)hipDeviceSynchronize();
   free_device(b);
   if (dev0 >= 0) (void)hipSetDevice(dev0);
+  b->layout = 0;
   if (variant == -1)
     assign_solo(b);
   else if (variant == 0)

@@ -66,6 +66,8 @@ _SIGS = {
     "dedisp_batch_destroy": (_i, [_p]),
     "dedisp_batch_get_variant": (_i, [_p, ctypes.POINTER(_i)]),
     "dedisp_batch_set_variant": (_i, [_p, _i]),
+    "dedisp_batch_get_layout": (_i, [_p, ctypes.POINTER(_i)]),
+    "dedisp_batch_set_layout": (_i, [_p, _i]),
     "dedisp_batch_autotune": (_i, [_p, _pp, _pp, _p, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
     "dedisp_server_create": (_i, [ctypes.c_size_t, _i, _pp]),
     "dedisp_server_add_beam": (_i, [_p, _p, _i64, ctypes.POINTER(_i)]),
@@ -272,6 +274,16 @@ def dedisp_batch_get_variant(batch: int) -> int:
 
 def dedisp_batch_set_variant(batch: int, variant: int) -> None:
     _check(lib.dedisp_batch_set_variant(batch, int(variant)), "dedisp_batch_set_variant")
+
+
+def dedisp_batch_get_layout(batch: int) -> int:
+    v = _i()
+    _check(lib.dedisp_batch_get_layout(batch, ctypes.byref(v)), "dedisp_batch_get_layout")
+    return v.value
+
+
+def dedisp_batch_set_layout(batch: int, layout: int) -> None:
+    _check(lib.dedisp_batch_set_layout(batch, int(layout)), "dedisp_batch_set_layout")
 
 
 def dedisp_batch_autotune(batch: int, ins, outs, stream=None):

@@ -168,6 +168,17 @@ def test_batch_create_checks(dd):
     # -1: every beam on its own
     dd.dedisp_batch_set_variant(b, -1)
     assert dd.dedisp_batch_get_variant(b) == -1
+    # graph layouts: 0-2 (host bookkeeping only before the first execute)
+    assert dd.dedisp_batch_get_layout(b) == 0
+    for layout in (1, 2, 0):
+        dd.dedisp_batch_set_layout(b, layout)
+        assert dd.dedisp_batch_get_layout(b) == layout
+    for bad in (-1, 3):
+        with pytest.raises(dd.DedispError):
+            dd.dedisp_batch_set_layout(b, bad)
+    dd.dedisp_batch_set_layout(b, 2)
+    dd.dedisp_batch_set_variant(b, -1)  # resets the layout
+    assert dd.dedisp_batch_get_layout(b) == 0
     dd.dedisp_batch_destroy(b)
 
 

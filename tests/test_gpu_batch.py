@@ -172,15 +172,27 @@ def test_batch_split_by_plan_variants(dd):
             for w, o, s in zip(beams, outs, solo):
                 assert np.array_equal(o.cpu().numpy().view(np.uint32), s), "beam %s replay %d" % (w.name, rep)
         assert dd.dedisp_batch_get_variant(batch) >= 1
-        # every beam launched on its own inside the graph
+        # every beam launched on its own inside the graph, in each layout of
+        # the graph's branches (balanced, one branch, one per staging kind)
         dd.dedisp_batch_set_variant(batch, -1)
         assert dd.dedisp_batch_get_variant(batch) == -1
-        for rep in range(2):
-            outs = [alloc_out(w) for w in beams]
-            dd.dedisp_batch_execute(batch, [t.data_ptr() for t in ins], [t.data_ptr() for t in outs], stream)
-            torch.cuda.synchronize()
-            for w, o, s in zip(beams, outs, solo):
-                assert np.array_equal(o.cpu().numpy().view(np.uint32), s), "beam %s per-beam replay %d" % (w.name, rep)
+        for layout in (0, 1, 2):
+            dd.dedisp_batch_set_layout(batch, layout)
+            for rep in range(2):
+                outs = [alloc_out(w) for w in beams]
+                dd.dedisp_batch_execute(batch, [t.data_ptr() for t in ins], [t.data_ptr() for t in outs], stream)
+                torch.cuda.synchronize()
+                for w, o, s in zip(beams, outs, solo):
+                    assert np.array_equal(o.cpu().numpy().view(np.uint32), s), \
+                        "beam %s per-beam layout %d replay %d" % (w.name, layout, rep)
+        # persistent groups in the per-kind layout
+        dd.dedisp_batch_set_variant(batch, 0)
+        dd.dedisp_batch_set_layout(batch, 2)
+        outs = [alloc_out(w) for w in beams]
+        dd.dedisp_batch_execute(batch, [t.data_ptr() for t in ins], [t.data_ptr() for t in outs], stream)
+        torch.cuda.synchronize()
+        for w, o, s in zip(beams, outs, solo):
+            assert np.array_equal(o.cpu().numpy().view(np.uint32), s), "beam %s groups by kind" % w.name
         v, ms = dd.dedisp_batch_autotune(batch, [t.data_ptr() for t in ins], [t.data_ptr() for t in outs])
         assert (v >= 1 or v == -1) and ms > 0
         outs = [alloc_out(w) for w in beams]
