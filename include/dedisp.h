@@ -138,7 +138,9 @@ int dedisp_plan_footprint(dedisp_plan plan, int64_t nsamp, uint64_t *in_bytes, u
  * number of variants compiled into the library; dedisp_variant_describe
  * writes (DMs per tile, samples per tile, threads per block) of a variant.
  * dedisp_plan_set_variant fails with DEDISP_ERR_INVALID_ARG if the variant's
- * on-chip window does not fit this plan's delay spread.
+ * on-chip window does not fit this plan's delay spread or the variant has no
+ * kernel for the plan's input type (some variants serve only float, or only
+ * half and 8-bit input).
  */
 int dedisp_variant_count(void);
 int dedisp_variant_describe(int variant, int *dms_per_tile, int *samples_per_tile, int *threads);

@@ -939,6 +939,9 @@ const Variant kVariants[] = {
     DEDISP_VARIANT_16(1, 16, 8, 1, 4, 2),   // 8 x 2016, 512 threads, 4 channels per stage
     DEDISP_VARIANT_16(1, 16, 8, 1, 8, 1),   // 8 x 2016, 512 threads, 8 channels per stage
     DEDISP_VARIANT_16(1, 16, 16, 1, 8, 2),  // 16 x 2016, 1024 threads, 8 channels per stage
+    // few trials a tile, for delay spreads too wide for the tiles above
+    DEDISP_VARIANT(1, 8, 2, 4, 1, 4),  // 2 x 4032, 512 threads, 1 channel per stage
+    DEDISP_VARIANT(1, 8, 1, 8, 1, 4),  // 1 x 8064, 512 threads, 1 channel per stage (any spread)
 };
 constexpr int kNumTiled = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -1012,7 +1015,7 @@ bool variant_fits(dedisp_plan p, int v) {
 }
 
 int default_variant(dedisp_plan p) {
-  static const int order[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14};
+  static const int order[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16};
   for (int v : order)
     if (v <= kNumTiled && variant_fits(p, v)) return v;
   return 0;

@@ -223,9 +223,12 @@ def test_fig4_sweep_shapes(dd, nchans, dm_max, dtype, nsamp, rows):
     sh, m = oracle.shift_table(nchans, band.f_top, band.df, band.tsamp, oracle.dm_grid(dm_max, nchans))
     plan = dd.Plan(nchans, band.f_top, band.df, band.tsamp, dms, dtype)
     assert plan.max_shift == m
-    # 2000 channels and trials fit a tile; at 256 the trials are too far apart
-    # (an 8-trial tile would span ~24k samples) and the direct kernel runs
-    assert (plan.variant >= 1) == (nchans == 2000)
+    # 2000 channels and trials fit an 8-trial tile; at 256 the trials are too
+    # far apart (an 8-trial tile would span ~24k samples) and the default is a
+    # tile of one or two trials
+    assert plan.variant >= 1
+    if nchans == 256:
+        assert dd.dedisp_variant_describe(plan.variant)[0] <= 2  # trials per tile
     g = torch.Generator(device="cuda")
     g.manual_seed(nchans + int(dm_max))
     if dtype == "u8":
@@ -237,7 +240,9 @@ def test_fig4_sweep_shapes(dd, nchans, dm_max, dtype, nsamp, rows):
     want = oracle.dedisperse(x, sh, nsamp, rows=rows)
     scale = None if dtype == "u8" else abs_sum(x, sh, nsamp, rows=rows)
     odt = torch.int32 if dtype == "u8" else torch.float32
-    for v in sorted({plan.variant, 0}) if nchans <= 256 else [plan.variant]:
+    # at 256 channels: the default, every other tiled variant that fits, and
+    # the direct kernel
+    for v in all_variants(dd, plan) if nchans <= 256 else [plan.variant]:
         plan.variant = v
         out = torch.full((nchans, nsamp), -7, dtype=odt, device="cuda")
         plan.execute(xin, out, nsamp, torch.cuda.current_stream())
