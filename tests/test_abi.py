@@ -143,12 +143,18 @@ def test_variants(dd):
     assert p.variant == 0
     with pytest.raises(dd.DedispError):
         p.variant = n
-    # a delay spread no tile can stage leaves only the direct kernel
+    # a delay spread no multi-trial tile can stage leaves the one-trial tile
+    # (whose window is its own samples only) and the direct kernel
     wide = dd.Plan(16, 150.0, 4.0, 327.68e-6, wl.dm_grid(4, 200.0), "f32")
-    assert wide.variant == 0
+    assert wide.variant >= 1 and dd.dedisp_variant_describe(wide.variant)[0] == 1
     for v in range(1, n):
-        with pytest.raises(dd.DedispError):
+        if dd.dedisp_variant_describe(v)[0] == 1:
             wide.variant = v
+        else:
+            with pytest.raises(dd.DedispError):
+                wide.variant = v
+    wide.variant = 0
+    assert wide.variant == 0
 
 
 def test_batch_create_checks(dd):
