@@ -19,6 +19,7 @@
 #include <atomic>
 #include <new>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <thread>
 #include <vector>
@@ -207,12 +208,20 @@ __attribute__((target("avx2"))) void tile256_u8(const Job& j, int d0, int d1, in
   }
 }
 
+// The widest vector code the host runs: 2 AVX-512, 1 AVX2, 0 plain C++.  The
+// environment variable DEDISP_CPU_ISA (0, 1 or 2) caps it, so that tests can
+// run every path on one machine.
 int isa_level() {
   static const int level = [] {
     __builtin_cpu_init();
-    if (__builtin_cpu_supports("avx512f") && __builtin_cpu_supports("avx512bw")) return 2;
-    if (__builtin_cpu_supports("avx2") && __builtin_cpu_supports("f16c")) return 1;
-    return 0;
+    int l = 0;
+    if (__builtin_cpu_supports("avx512f") && __builtin_cpu_supports("avx512bw"))
+      l = 2;
+    else if (__builtin_cpu_supports("avx2") && __builtin_cpu_supports("f16c"))
+      l = 1;
+    const char* cap = std::getenv("DEDISP_CPU_ISA");
+    if (cap != nullptr && cap[0] >= '0' && cap[0] <= '2' && cap[1] == '\0') l = std::min(l, cap[0] - '0');
+    return l;
   }();
   return level;
 }
