@@ -157,12 +157,17 @@ def test_edge_shapes(dd, nchans, ndm, nsamp):
     xu = rng.integers(0, 256, (nchans, nsamp + m)).astype(np.uint8)
     want = oracle.dedisperse(x, sh, nsamp)
     wantu = oracle.dedisperse(xu, sh, nsamp)
+    xh = x.astype(np.float16)  # half input: the tail of 1-7 samples past the last 16 bytes
+    wanth = oracle.dedisperse(xh, sh, nsamp)
     p = dd.Plan(nchans, band.f_top, band.df, band.tsamp, dms, "f32")
     pu = dd.Plan(nchans, band.f_top, band.df, band.tsamp, dms, "u8")
+    ph = dd.Plan(nchans, band.f_top, band.df, band.tsamp, dms, "f16")
     for v in all_variants(dd, p):
         check_float(run(p, x, nsamp, variant=v), want, abs_sum(x, sh, nsamp))
     for v in all_variants(dd, pu):
         assert np.array_equal(run(pu, xu, nsamp, variant=v).astype(np.int64), wantu)
+    for v in all_variants(dd, ph):
+        check_float(run(ph, xh, nsamp, variant=v), wanth, abs_sum(xh, sh, nsamp))
 
 
 @pytest.mark.parametrize("dtype", ["u8", "f32"])
