@@ -47,9 +47,9 @@ def wait(dd, server, ticket, timeout=30.0):
         time.sleep(0.001)
 
 
-def run_stream(dd, specs, nblocks, mix=True):
+def run_stream(dd, specs, nblocks, mix=True, variant=None):
     """specs: list of (seed, nchans, ndm, step, dtype, block).  Returns per-beam
-    lists of host outputs of every block."""
+    lists of host outputs of every block (every plan on ``variant`` if given)."""
     import torch
     server = dd.dedisp_server_create(8 << 30, 6)
     try:
@@ -57,6 +57,8 @@ def run_stream(dd, specs, nblocks, mix=True):
         for (seed, nchans, ndm, step, dtype, block) in specs:
             band, dms, sh, m = beam_setup(seed, nchans, ndm, step, dtype, block)
             plan = dd.Plan(nchans, band.f_top, band.df, band.tsamp, dms, dtype)
+            if variant is not None:
+                plan.variant = variant
             bid = dd.dedisp_server_add_beam(server, plan.handle, block)
             data = stream_data(seed, nchans, block * nblocks, dtype)
             blocks = [torch.from_numpy(np.ascontiguousarray(data[:, b * block:(b + 1) * block])).pin_memory()
@@ -120,6 +122,36 @@ def test_stream_equals_one_shot(dd):
     a = np.concatenate([o.cpu().numpy() for o in alone[0]["outs"]], axis=1)
     b = np.concatenate([o.cpu().numpy() for o in mixed[0]["outs"]], axis=1)
     assert np.array_equal(a, b)
+
+
+def test_stream_every_variant(dd):
+    """Each tile variant (and the direct kernel) on ring rows: two small beams,
+    a short block, so that the longest tiles' windows reach past the ring
+    (those loads return zeros and feed only samples past the block), every
+    block equal to the oracle's streaming reference."""
+    nblocks = 3
+    specs = [(11, 48, 30, 1.0, "u8", 512), (12, 40, 24, 1.0, "f32", 512), (13, 40, 24, 1.0, "f16", 512)]
+    ran = []
+    for v in range(dd.dedisp_variant_count()):
+        for spec in specs:
+            try:
+                beams = run_stream(dd, [spec], nblocks, variant=v)
+            except dd.DedispError:
+                continue  # the variant does not serve this input type
+            ran.append((v, spec[4]))
+            bm = beams[0]
+            B, m = bm["block"], bm["m"]
+            got = np.concatenate([o.cpu().numpy() for o in bm["outs"]], axis=1)
+            want = np.concatenate([oracle.stream_reference(bm["data"], bm["sh"], m, B, b) for b in range(nblocks)],
+                                  axis=1)
+            if bm["dtype"] == "u8":
+                assert np.array_equal(got.astype(np.int64), want), "variant %d" % v
+            else:
+                padded = np.concatenate([np.zeros((bm["data"].shape[0], m), bm["data"].dtype), bm["data"]], axis=1)
+                check_float(got, want, abs_sum(padded, bm["sh"], B * nblocks))
+    # every variant ran for the input types it serves (the float-only and
+    # 16-bit-only ones for one or two of the three)
+    assert len(ran) >= 2 * dd.dedisp_variant_count(), ran
 
 
 def test_admission_by_memory(dd):
