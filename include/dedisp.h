@@ -346,7 +346,8 @@ int dedisp_batch_set_layout(dedisp_batch batch, int layout);
  * separate persistent kernels); the split that follows each plan's own
  * variant (set or tuned with dedisp_autotune); and every beam launched on its
  * own with its plan's variant, the launches captured in the graph in each
- * layout (dedisp_batch_get_layout).  Keeps the fastest; best_variant is then
+ * layout (dedisp_batch_get_layout); the persistent splits are timed in layout
+ * 0, whatever layout was set before.  Keeps the fastest; best_variant is then
  * the variant of the persistent kernel that carries the most work (-1 if the
  * per-beam launches won).  Synchronises the
  * stream.  The outputs are overwritten (with correct results).  best_ms may

@@ -554,6 +554,7 @@ extern "C" int dedisp_batch_autotune(dedisp_batch b, const void* const* ins, voi
   if (b == nullptr || best_variant == nullptr) return DEDISP_ERR_INVALID_ARG;
   int st = check_ptrs(b, ins, outs);
   if (st != DEDISP_OK) return st;
+  b->layout = 0;  // the groups are timed on balanced branches, whatever was set before
   hipStream_t stream = static_cast<hipStream_t>(stream_v);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
