@@ -1,8 +1,9 @@
 """The allocation-free entry point (dedisp_execute_static) against
 dedisp_execute: two calls in a row on the same device (the second smaller),
 8-bit input (whose widened copy lives in the library's static scratch) and
-float32 input, every output compared; and its refusals (too large for the
-scratch, device tables not yet created)."""
+float32 input, every output compared; the entry captured into a HIP graph
+and replayed; and its refusals (too large for the scratch, device tables not
+yet created)."""
 import numpy as np
 import pytest
 
@@ -57,6 +58,45 @@ def test_static_entry_matches_execute(dd, dtype):
         else:
             scale = oracle.dedisperse(np.abs(x), sh, nsamp, rows=rows)
             assert np.all(np.abs(b[rows] - want) <= 1e-5 * scale)
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_static_entry_in_a_captured_graph(dd, dtype):
+    """Captured into a HIP graph (nothing is allocated, so capture records
+    only its kernels) and replayed three times, new input written eagerly
+    between the replays: every replay equals dedisp_execute on that input."""
+    import torch
+    nsamp = 3001
+    plan, sh, x, xin, ref, got = case(dd, dtype, 256, 70, nsamp, 4)
+    stream = torch.cuda.current_stream()
+    plan.execute(xin, ref, nsamp, stream)  # device tables
+    dd.dedisp_execute_static(plan.handle, xin.data_ptr(), got.data_ptr(), nsamp, stream)  # warm-up
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        dd.dedisp_execute_static(plan.handle, xin.data_ptr(), got.data_ptr(), nsamp, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(6)
+    for k in range(3):
+        if dtype == "u8":
+            x2 = rng.integers(0, 256, x.shape).astype(np.uint8)
+        else:
+            x2 = rng.standard_normal(x.shape).astype(np.float32)
+        xin.copy_(torch.from_numpy(x2))
+        got.fill_(-9)
+        graph.replay()
+        plan.execute(xin, ref, nsamp, stream)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), "replay %d" % k
+    rows = np.array([0, 35, 69])
+    want = oracle.dedisperse(x2, sh, nsamp, rows=rows)
+    b = got.cpu().numpy()
+    if dtype == "u8":
+        assert np.array_equal(b[rows].astype(np.int64), want)
+    else:
+        scale = oracle.dedisperse(np.abs(x2), sh, nsamp, rows=rows)
+        assert np.all(np.abs(b[rows] - want) <= 1e-5 * scale)
+    del graph
 
 
 def test_static_entry_refusals(dd):
