@@ -32,7 +32,8 @@ Functions and the passages they follow:
   "Introduction": the pipeline ends in detection; Figure 3: the recovered pulse
   at its trial DM): per trial mean and standard deviation, boxcar S/N for
   widths 1, 2, 4, ..., the best (S/N, time) per width, the candidates above a
-  threshold.  The paper gives no formula; this is the reading stated there.
+  threshold.  The paper gives no formula; the function's docstring states the
+  reading used.
 
 Every function here is pinned by ``tests/test_oracle_pins.py`` against results
 the mathematics fixes (exact rational arithmetic, closed forms, invariants, an
