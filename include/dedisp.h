@@ -391,6 +391,9 @@ int dedisp_server_add_beam(dedisp_server server, dedisp_plan plan, int64_t block
  *            (hipHostMalloc) for the copy to overlap.
  *   out_dev  device pointer to [ndm][B] outputs; must stay allocated until done
  *   ticket   receives an id for dedisp_poll
+ * The server's streams do not wait for work the caller queued elsewhere: a
+ * block or output buffer that device work of the caller writes (a copy, a
+ * fill) must be complete before the submission.
  * DEDISP_ERR_AGAIN: not admitted (budget or slots); nothing was queued.
  */
 int dedisp_submit(dedisp_server server, int beam_id, const void *block, void *out_dev, uint64_t *ticket);

@@ -209,6 +209,8 @@ def test_server_meerkat_shape(dd):
             for k in range(nblocks):
                 for i in beam_ids:
                     out = torch.full((4096, B), -3, dtype=torch.int32, device="cuda")
+                    # the server's streams do not wait for torch's: the fill must be done
+                    torch.cuda.current_stream().synchronize()
                     while True:
                         t = dd.dedisp_submit(server, bids[i], blocks[i][k].data_ptr(), out.data_ptr())
                         if t is not None:

@@ -72,6 +72,8 @@ def run_stream(dd, specs, nblocks, mix=True, variant=None):
             bm = beams[i]
             odt = torch.int32 if bm["dtype"] == "u8" else torch.float32
             out = torch.full((bm["ndm"], bm["block"]), -3, dtype=odt, device="cuda")
+            # the server's streams do not wait for torch's: the fill must be done
+            torch.cuda.current_stream().synchronize()
             while True:
                 t = dd.dedisp_submit(server, bm["bid"], bm["blocks"][b].data_ptr(), out.data_ptr())
                 if t is not None:
