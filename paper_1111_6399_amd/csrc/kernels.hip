@@ -552,8 +552,13 @@ __device__ __forceinline__ void tile_dma(const TiledArgs& a, int dm_tile, int t_
         if (ring == 0) {
           lds_dma_k(k, lds, u + lane16, rs);
         } else {
-          // offsets stay below twice the ring (rings are longer than any
-          // window plus a tile), so one subtraction wraps them
+          // A window starts below twice the ring; rings hold the history,
+          // the block and 4608 more samples, so one subtraction wraps every
+          // offset the block's outputs need.  Only the one-trial tile (8064
+          // samples) reads further past the block: those offsets wrap once
+          // more below, or read zeros through the descriptor's range check,
+          // and feed outputs past the block only.  Offsets stay below 2^32
+          // (launch_rows takes the direct kernel for longer rings).
           uint32_t w = u >= ring ? u - ring : u;
           if (w + 1024u * static_cast<uint32_t>(k < 4 ? k : 4) <= ring) {
             lds_dma_k(k, lds, w + lane16, rs);
@@ -1127,7 +1132,9 @@ int launch_rows(dedisp_plan p, int v, const StagedRows& rows, void* out, int64_t
   DeviceTables* dt = nullptr;
   int st = device_tables(p, dev, &dt);
   if (st != DEDISP_OK) return st;
-  if (v > 0 && !offsets_fit(p, rows.pitch)) v = 0;
+  // ring windows are addressed from the ring's start up to twice its length
+  // plus a tile, in 32-bit byte offsets
+  if (v > 0 && !offsets_fit(p, rows.ring > 0 ? 2 * rows.pitch + 8192 : rows.pitch)) v = 0;
   if (v == 0) {
     // same channel order and float conversion as on raw input
     switch (p->dtype) {

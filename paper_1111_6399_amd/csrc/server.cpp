@@ -72,8 +72,10 @@ struct Beam {
 };
 
 // Ring length for a beam: the history and a block, plus the samples a tile
-// may read past the block (up to 4032 samples, its halo and the rounding of
-// its loads to 1 KB), a multiple of 8 samples.
+// may read past the block (4032 samples, its halo and the rounding of its
+// loads to 1 KB; the one-trial tile of 8064 samples reads further, and those
+// reads wrap or return zeros and feed only outputs past the block), a
+// multiple of 8 samples.
 int64_t ring_samples(int64_t max_shift, int64_t block) { return (max_shift + block + 4608 + 7) / 8 * 8; }
 
 }  // namespace
